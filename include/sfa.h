@@ -1,0 +1,209 @@
+/*
+ * sfa.h -- C ABI of the MI355X (gfx950) simultaneous-finite-automaton matcher.
+ *
+ * Method: Sin'ya, Matsuzaki, Sassa, "Simultaneous Finite Automata: An
+ * Efficient Data-Parallel Model for Regular Expression Matching" (ICPP 2013).
+ *
+ *   - A D-SFA state is a transformation f: Q -> Q of the DFA's states
+ *     (Definition 3, Section 4.1, with singleton images).
+ *   - Reading a byte is one table lookup f <- delta_s[f, sigma], starting from
+ *     the identity f_I (Algorithm 5, Section 5.2).
+ *   - Chunk results compose by reverse composition (f . g)(q) = g(f(q))
+ *     (Section 2.1), which is associative, so the input may be split anywhere
+ *     (Lemma 1 and Theorem 2, Section 4.3).
+ *   - The answer is f_fin(q0) and whether it is an accepting DFA state.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *   - Every call returns sfa_status; SFA_OK is 0.  No call aborts the process,
+ *     throws across the ABI or prints.  sfa_last_error() returns a message for
+ *     the calling thread's last failure.
+ *   - "d_" pointers are device pointers (HIP device memory on the current
+ *     device); all other pointers are host pointers.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it asynchronously; results are valid once
+ *     the stream has been synchronised.
+ *   - The caller owns all device memory: inputs, outputs, workspaces and the
+ *     table buffer.  The library never allocates device memory.  Library
+ *     handles (sfa_compiled, sfa_table) are host objects.
+ *   - Sizes and offsets are 64-bit: an input may exceed 4 GiB.
+ *   - States are reported in the canonical numbering of the minimal complete
+ *     DFA: breadth-first from the start state (id 0) following bytes 0..255 in
+ *     ascending order, each state numbered when first reached.
+ *   - Thread safety: distinct handles may be used from distinct threads; a
+ *     loaded table may be used by many streams at once.  Calls that share one
+ *     workspace must not overlap in time.
+ *
+ * Regex syntax (whole-input membership, Definition of L(A), Section 2.2):
+ *   bytes are the alphabet; "." is any byte (newline too); [..] and [^..]
+ *   with ranges; escapes \n \t \r \f \v \0 \xHH \d \D \w \W \s \S and a
+ *   backslash before punctuation; ( ) | * + ? {n} {n,} {,m} {n,m} (bounds at
+ *   most 1000; a "{" that does not begin a valid bound is a literal);
+ *   empty alternatives are allowed; stacked quantifiers are errors.
+ *   A search is written with explicit ".*" on both sides.
+ */
+#ifndef SFA_H
+#define SFA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFA_ABI_VERSION 1u
+
+typedef enum sfa_status {
+    SFA_OK = 0,
+    SFA_ERR_INVALID_ARG = 1,       /* null pointer, bad size, out-of-range table entry */
+    SFA_ERR_PARSE = 2,             /* regex syntax error (message via sfa_last_error) */
+    SFA_ERR_DFA_TOO_LARGE = 3,     /* subset construction exceeded the DFA state limit */
+    SFA_ERR_OVER_CAP = 4,          /* D-SFA exceeds the state cap */
+    SFA_ERR_NO_DEVICE = 5,         /* no HIP device visible */
+    SFA_ERR_UNSUPPORTED_ARCH = 6,  /* current device is not gfx950 */
+    SFA_ERR_BUFFER_TOO_SMALL = 7,  /* device buffer or workspace smaller than required */
+    SFA_ERR_HIP = 8,               /* a HIP runtime call failed (message has the HIP error) */
+    SFA_ERR_NO_SFA = 9,            /* table has no D-SFA part: use the speculative matcher */
+    SFA_ERR_HOST_ALLOC = 10        /* host memory allocation failed */
+} sfa_status;
+
+/* Result of one match: final canonical DFA state and its acceptance. */
+typedef struct sfa_result {
+    uint32_t state;
+    uint32_t accept;               /* 1 if state is accepting, else 0 */
+} sfa_result;
+
+const char *sfa_status_string(sfa_status s);
+const char *sfa_last_error(void);
+uint32_t    sfa_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Host compiler: regex -> minimal canonical DFA -> byte classes -> D-SFA.
+ *
+ *   Position (Glushkov) NFA, subset construction (Algorithm 1, Section 2.3)
+ *   over byte classes, Hopcroft minimisation, canonical renumbering, then the
+ *   correspondence construction with the deterministic simplification
+ *   (Algorithm 4, Section 5.1): worklist first-in first-out, classes in
+ *   ascending order, the identity mapping is D-SFA state 0.
+ *
+ *   sfa_cap: maximum number of D-SFA states (identity included).  If the
+ *   construction exceeds it, or sfa_cap is 0, sfa_compile still succeeds with
+ *   the DFA only (info.n_sfa == 0); such a table is matched with
+ *   sfa_match_speculative.  dfa_cap bounds the subset construction
+ *   (SFA_ERR_DFA_TOO_LARGE beyond it; 0 = 65535, the maximum).
+ * ---------------------------------------------------------------------- */
+typedef struct sfa_compiled sfa_compiled;
+
+typedef struct sfa_compile_info {
+    uint32_t n_dfa;        /* states of the minimal complete DFA (sink included) */
+    uint32_t n_sfa;        /* D-SFA states, identity included; 0 if not built */
+    uint32_t n_classes;    /* byte classes (coarsest partition with equal DFA columns) */
+    uint32_t q0;           /* start state: always 0 in the canonical numbering */
+    uint32_t n_positions;  /* positions of the Glushkov NFA */
+    uint32_t sfa_over_cap; /* 1 if the D-SFA construction stopped at the cap */
+    double   dfa_seconds;  /* host time of parse + NFA + DFA + minimisation */
+    double   sfa_seconds;  /* host time of the D-SFA construction */
+} sfa_compile_info;
+
+sfa_status sfa_compile(const char *pattern, size_t pattern_len, uint32_t sfa_cap,
+                       uint32_t dfa_cap, sfa_compiled **out);
+sfa_status sfa_compiled_info(const sfa_compiled *c, sfa_compile_info *out);
+void       sfa_compiled_free(sfa_compiled *c);
+
+/* Host arrays describing a DFA and (optionally) its D-SFA.
+ *   byte_class[256]             class id (< n_classes) of each byte value
+ *   dfa_next[n_dfa*n_classes]   delta(q, c) at [q*n_classes + c]
+ *   dfa_accept[n_dfa]           0/1
+ *   sfa_next[n_sfa*n_classes]   delta_s(f, c); state 0 must be the identity
+ *   sfa_map[n_sfa*n_dfa]        f(q) at [f*n_dfa + q]
+ * n_sfa == 0 means no D-SFA (sfa_next, sfa_map may be NULL).
+ * Limits: n_dfa <= 65535, n_sfa <= 16777215, 1 <= n_classes <= 256, q0 < n_dfa. */
+typedef struct sfa_table_desc {
+    uint32_t abi_version;
+    uint32_t n_dfa, n_sfa, n_classes, q0;
+    const uint8_t  *byte_class;
+    const uint32_t *dfa_next;
+    const uint8_t  *dfa_accept;
+    const uint32_t *sfa_next;
+    const uint32_t *sfa_map;
+} sfa_table_desc;
+
+/* Descriptor whose arrays point into c; valid while c lives. */
+sfa_status sfa_compiled_desc(const sfa_compiled *c, sfa_table_desc *out);
+
+/* ------------------------------------------------------------------------
+ * Device tables.
+ *
+ *   sfa_table_device_bytes: size of the device buffer sfa_load_table needs.
+ *   sfa_load_table: validates every entry (out-of-range values and a state 0
+ *     that is not the identity give SFA_ERR_INVALID_ARG), packs the arrays
+ *     into the layout the kernels read (narrowest entry width; the walk table
+ *     is copied into LDS at kernel start when it fits the LDS budget, else it
+ *     is read from global memory through L2) and enqueues one host-to-device
+ *     copy into d_buf on stream.  The packed host image is owned by the
+ *     handle, so desc's arrays may be freed on return.  d_buf must stay
+ *     allocated, and unmodified, while the handle is used.
+ *   opts may be NULL (defaults).  force_global = 1 keeps the walk table in
+ *   global memory even when it would fit LDS.
+ *   sfa_free_table frees the host handle only; the caller frees d_buf after
+ *   work that uses it has finished.
+ * ---------------------------------------------------------------------- */
+typedef struct sfa_table sfa_table;
+
+typedef struct sfa_load_options {
+    uint32_t force_global;   /* 0: LDS when it fits; 1: always global */
+    uint32_t lds_budget;     /* bytes of LDS the walk table may take; 0 = default (96 KiB) */
+    uint32_t no_monoid;      /* 1: never build the D-SFA product table */
+    uint32_t reserved;
+} sfa_load_options;
+
+typedef struct sfa_table_info {
+    uint32_t n_dfa, n_sfa, n_classes, q0;
+    uint32_t next_bytes;     /* width of a walk-table entry: 1, 2 or 4 */
+    uint32_t map_bytes;      /* width of a mapping entry: 1, 2 or 4 */
+    uint32_t table_in_lds;   /* 1 if the walk table is staged into LDS */
+    uint32_t has_monoid;     /* 1 if the D-SFA product table mul[a][b] is present */
+    uint64_t device_bytes;   /* bytes used in d_buf */
+} sfa_table_info;
+
+sfa_status sfa_table_device_bytes(const sfa_table_desc *desc, const sfa_load_options *opts,
+                                  size_t *out_bytes);
+sfa_status sfa_load_table(const sfa_table_desc *desc, const sfa_load_options *opts,
+                          void *d_buf, size_t d_bytes, void *stream, sfa_table **out);
+sfa_status sfa_table_get_info(const sfa_table *t, sfa_table_info *out);
+sfa_status sfa_free_table(sfa_table *t);
+
+/* ------------------------------------------------------------------------
+ * Single-stream matching (Algorithm 5, Section 5.2).
+ *
+ *   d_in[0..n) is split into n_chunks chunks [c*L, min((c+1)*L, n)),
+ *   L = ceil(n / n_chunks); chunk c's D-SFA state is computed from f_I and the
+ *   chunk results are composed in text order; the result is f_fin(q0).  One
+ *   lane owns one chunk and may walk it as several interleaved pieces, which
+ *   Theorem 2 allows; n_chunks = 0 lets the library choose.  n_chunks > n is
+ *   legal (empty chunks are the identity); n = 0 gives (q0, accept(q0)).
+ *   Any alignment of d_in is accepted.
+ *
+ *   Workspace: sfa_match_workspace_bytes() bytes of device memory, which must
+ *   be zero-filled before its first use; each call leaves its control word
+ *   zero again, so a workspace is reused without clearing.  Calls sharing a
+ *   workspace must not overlap.  d_out receives one sfa_result.
+ * ---------------------------------------------------------------------- */
+sfa_status sfa_match_workspace_bytes(const sfa_table *t, uint64_t n, uint32_t n_chunks,
+                                     size_t *out_bytes);
+sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
+                     void *d_ws, size_t ws_bytes, sfa_result *d_out, void *stream);
+
+/* Speculative parallel DFA (Algorithm 3, Section 3): per chunk, every DFA
+ * state is simulated as a possible start (|Q| lookups per byte), giving the
+ * chunk's mapping T_i; the mappings are composed as in sfa_match.  Works for
+ * every table, with or without a D-SFA part; same arguments, same result. */
+sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64_t n,
+                                 uint32_t n_chunks, void *d_ws, size_t ws_bytes,
+                                 sfa_result *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFA_H */

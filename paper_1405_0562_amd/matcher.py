@@ -1,0 +1,164 @@
+"""Python face of the SFA matcher: compile, load, match.
+
+Every step of matching runs in libsfa.so (host compiler in C++, kernels in
+HIP); this module only marshals arguments.  PyTorch provides device memory
+and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import check, lib
+
+DEFAULT_SFA_CAP = 65535
+
+
+@dataclass
+class CompileInfo:
+    n_dfa: int
+    n_sfa: int
+    n_classes: int
+    q0: int
+    n_positions: int
+    sfa_over_cap: bool
+    dfa_seconds: float
+    sfa_seconds: float
+
+
+class Compiled:
+    """Result of the host compiler: canonical minimal DFA and (if built) its D-SFA."""
+
+    def __init__(self, pattern: str, sfa_cap: int = DEFAULT_SFA_CAP, dfa_cap: int = 0):
+        self.pattern = pattern
+        raw = pattern.encode("latin-1")
+        h = ctypes.c_void_p()
+        check(lib().sfa_compile(raw, len(raw), sfa_cap, dfa_cap, ctypes.byref(h)))
+        self._h = h
+        ci = _capi.CompileInfo()
+        check(lib().sfa_compiled_info(self._h, ctypes.byref(ci)))
+        self.info = CompileInfo(ci.n_dfa, ci.n_sfa, ci.n_classes, ci.q0, ci.n_positions,
+                                bool(ci.sfa_over_cap), ci.dfa_seconds, ci.sfa_seconds)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().sfa_compiled_free(h)
+            self._h = None
+
+    def desc(self) -> _capi.TableDesc:
+        d = _capi.TableDesc()
+        check(lib().sfa_compiled_desc(self._h, ctypes.byref(d)))
+        return d
+
+    def arrays(self) -> dict:
+        """Copies of the host tables (for inspection and tests)."""
+        d = self.desc()
+        n, m, C = d.n_dfa, d.n_sfa, d.n_classes
+
+        def arr(ptr, count, dtype):
+            if count == 0 or not ptr:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dtype, copy=True)
+
+        return {
+            "byte_class": arr(d.byte_class, 256, np.int64),
+            "dfa_next": arr(d.dfa_next, n * C, np.int64).reshape(n, C),
+            "dfa_accept": arr(d.dfa_accept, n, np.int64).astype(bool),
+            "sfa_next": arr(d.sfa_next, m * C, np.int64).reshape(m, C),
+            "sfa_map": arr(d.sfa_map, m * n, np.int64).reshape(m, n),
+            "q0": d.q0,
+        }
+
+
+def compile(pattern: str, sfa_cap: int = DEFAULT_SFA_CAP, dfa_cap: int = 0) -> Compiled:  # noqa: A001
+    return Compiled(pattern, sfa_cap, dfa_cap)
+
+
+def _stream_ptr(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Table:
+    """A compiled automaton resident in device memory (HBM)."""
+
+    def __init__(self, compiled: Compiled, device=None, force_global: bool = False, lds_budget: int = 0,
+                 stream=None):
+        self.compiled = compiled
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        desc = compiled.desc()
+        opts = _capi.LoadOptions(int(force_global), int(lds_budget), 0, 0)
+        nbytes = ctypes.c_size_t()
+        check(lib().sfa_table_device_bytes(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(nbytes)))
+        with torch.cuda.device(self.device):
+            self.buf = torch.empty(max(256, nbytes.value), dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            check(lib().sfa_load_table(ctypes.byref(desc), ctypes.byref(opts), ctypes.c_void_p(self.buf.data_ptr()),
+                                       nbytes.value, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+            self._h = h
+        ti = _capi.TableInfo()
+        check(lib().sfa_table_get_info(self._h, ctypes.byref(ti)))
+        self.info = {f: getattr(ti, f) for f, _ in _capi.TableInfo._fields_}
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().sfa_free_table(h)
+            self._h = None
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def workspace(self, n: int, n_chunks: int, stream=None) -> torch.Tensor:
+        """A zero-filled workspace large enough for (n, n_chunks), cached per stream.
+
+        The kernels leave the workspace's control word zero after every call,
+        so a cached workspace is reused without clearing; calls on one stream
+        never overlap.
+        """
+        need = ctypes.c_size_t()
+        check(lib().sfa_match_workspace_bytes(self._h, n, n_chunks, ctypes.byref(need)))
+        key = _stream_ptr(stream)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need.value:
+            ws = torch.zeros(max(need.value, 4096), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+
+def load(compiled: Compiled, **kw) -> Table:
+    return Table(compiled, **kw)
+
+
+def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: torch.Tensor | None, stream):
+    if data.dtype != torch.uint8 or not data.is_cuda or data.dim() != 1 or not data.is_contiguous():
+        raise ValueError("data must be a contiguous 1-D torch.uint8 tensor on a HIP device")
+    if data.device != table.device:
+        raise ValueError("data and table are on different devices")
+    n = data.numel()
+    ws = table.workspace(n, n_chunks, stream)
+    if out is None:
+        out = torch.empty(2, dtype=torch.int32, device=table.device)
+    check(getattr(lib(), fn_name)(table.handle, ctypes.c_void_p(data.data_ptr() if n else 0), n, n_chunks,
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(_stream_ptr(stream))))
+    return out
+
+
+def match(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor | None = None,
+          stream=None) -> torch.Tensor:
+    """Algorithm 5 on the device; returns int32[2] = (final state, accept) on the device."""
+    return _match("sfa_match", table, data, n_chunks, out, stream)
+
+
+def match_speculative(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """Algorithm 3 on the device; same result as ``match``."""
+    return _match("sfa_match_speculative", table, data, n_chunks, out, stream)

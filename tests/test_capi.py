@@ -1,0 +1,80 @@
+"""The C ABI: every symbol declared in include/sfa.h is exported and bound,
+and the host-side argument validation of the table loader (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1405_0562_amd as sfa
+from paper_1405_0562_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[a-z_][\w \*]*?\b(sfa_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = _capi.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert names == set(_capi.SIGNATURES)
+
+
+def test_status_strings_and_version():
+    L = _capi.lib()
+    assert L.sfa_abi_version() == 1
+    for s in range(11):
+        assert L.sfa_status_string(s)
+
+
+def _desc_from(c):
+    return c.desc()
+
+
+def test_loader_validation_without_gpu():
+    L = _capi.lib()
+    c = sfa.compile("(ab)*")
+    d = c.desc()
+    nbytes = ctypes.c_size_t()
+    assert L.sfa_table_device_bytes(ctypes.byref(d), None, ctypes.byref(nbytes)) == 0
+    assert nbytes.value > 0 and nbytes.value % 256 == 0
+    # out-of-range entries are rejected before any device work
+    arr = c.arrays()
+    nxt = np.ascontiguousarray(arr["sfa_next"].astype(np.uint32).ravel())
+    nxt[3] = 99
+    bad = _capi.TableDesc(1, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
+                          nxt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), d.sfa_map)
+    assert L.sfa_table_device_bytes(ctypes.byref(bad), None, ctypes.byref(nbytes)) == 1
+    # state 0 must be the identity
+    mp = np.ascontiguousarray(arr["sfa_map"].astype(np.uint32).ravel())
+    mp[0], mp[1] = mp[1], mp[0]
+    bad2 = _capi.TableDesc(1, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
+                           d.sfa_next, mp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    assert L.sfa_table_device_bytes(ctypes.byref(bad2), None, ctypes.byref(nbytes)) == 1
+    assert b"identity" in L.sfa_last_error()
+    bad3 = _capi.TableDesc(2, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
+                           d.sfa_next, d.sfa_map)
+    assert L.sfa_table_device_bytes(ctypes.byref(bad3), None, ctypes.byref(nbytes)) == 1
+
+
+def test_null_arguments_are_errors():
+    L = _capi.lib()
+    h = ctypes.c_void_p()
+    assert L.sfa_compile(None, 3, 10, 0, ctypes.byref(h)) == 1
+    assert L.sfa_match(None, None, 0, 0, None, 0, None, None) == 1
+    assert L.sfa_match_speculative(None, None, 0, 0, None, 0, None, None) == 1
+    assert L.sfa_load_table(None, None, None, 0, None, ctypes.byref(h)) == 1

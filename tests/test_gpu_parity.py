@@ -1,0 +1,188 @@
+"""GPU parity: the HIP matcher (through the C ABI) against the CPU oracle.
+
+Bit-exact comparison of (final canonical DFA state, accept) on seeded
+synthetic inputs: the oracle builds its own DFA from the regex and runs
+Algorithm 2 in plain C; the GPU path uses the product's host compiler and
+kernels.  Covers every workload at oracle-friendly sizes plus the full sizes
+of the single-stream workloads in the launch configuration the benchmark
+times, and the edge cases (empty and tiny inputs, ragged tails, unaligned
+base pointers, more chunks than bytes, all byte values, global-memory tables,
+tables without a D-SFA).
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.automata import compile_regex
+from oracle import scan as oscan
+
+pytestmark = pytest.mark.gpu
+
+sfa = pytest.importorskip("paper_1405_0562_amd")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_dfa(rx):
+    d = compile_regex(rx)
+    return d, oscan.table_u32(d)
+
+
+def oracle_result(rx, data):
+    d, tab = oracle_dfa(rx)
+    q = oscan.scan(d, data, table=tab)
+    return [q, int(d.accept[q])]
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_table(rx, force_global=False, sfa_cap=65535):
+    c = sfa.compile(rx, sfa_cap=sfa_cap)
+    return sfa.load(c, force_global=force_global)
+
+
+def to_device(data: np.ndarray, offset: int = 0) -> torch.Tensor:
+    n = data.size
+    buf = torch.empty(n + offset + 16, dtype=torch.uint8, device="cuda")
+    view = buf[offset:offset + n]
+    if n:
+        view.copy_(torch.from_numpy(np.ascontiguousarray(data)))
+    return view
+
+
+def run(rx, data, n_chunks=0, offset=0, speculative=False, force_global=False, sfa_cap=65535, x=None):
+    t = gpu_table(rx, force_global, sfa_cap)
+    say(rx[:40], "n=%d" % data.size, "chunks=%d" % n_chunks, "off=%d" % offset,
+        "spec" if speculative else "sfa", "global" if force_global else "")
+    if x is None:
+        x = to_device(data, offset)
+    fn = sfa.match_speculative if speculative else sfa.match
+    out = fn(t, x, n_chunks=n_chunks)
+    return out.tolist()
+
+
+def check(rx, data, **kw):
+    got = run(rx, data, **kw)
+    want = oracle_result(rx, data)
+    assert got == want, (rx, data.size, kw, got, want)
+    return got
+
+
+# --------------------------------------------------------------------------
+# single-stream workloads
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(16))
+def test_c1_all_seeds(seed):
+    data = W.c1_input(seed)
+    got = check(W.REGEX_C1, data, n_chunks=256)
+    check(W.REGEX_C1, data, n_chunks=256, speculative=True)
+    assert got[1] in (0, 1)
+
+
+def test_c1_accept_and_reject_both_occur():
+    res = {oracle_result(W.REGEX_C1, W.c1_input(s))[1] for s in range(16)}
+    assert res == {0, 1}
+
+
+@pytest.mark.parametrize("n_chunks", [0, 1, 7, 256, 4096, 65536])
+def test_c2_reduced(n_chunks):
+    data = W.c2_input(3, n=(1 << 22) + 13)
+    check(W.REGEX_C2, data, n_chunks=n_chunks)
+    check(W.REGEX_C2, data, n_chunks=n_chunks, speculative=True)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c2_full_size_bench_config(seed):
+    data = W.c2_input(seed)                       # 256 MiB
+    x = to_device(data)
+    want = oracle_result(W.REGEX_C2, data)
+    assert run(W.REGEX_C2, data, n_chunks=65536, x=x) == want
+    assert run(W.REGEX_C2, data, n_chunks=65536, speculative=True, x=x) == want
+    assert run(W.REGEX_C2, data, n_chunks=0, x=x) == want
+    # closed form: accept iff the fifth byte from the end is 'a'
+    assert want[1] == int(data[-5] == ord("a"))
+
+
+def test_c3_reduced_with_and_without_plants():
+    kws = W.c3_keywords(0)
+    rx = W.c3_regex(kws)
+    for rate in (0.0, 2e-6):
+        data = W.c3_input(5, 1 << 24, kws, rate=rate)
+        check(rx, data, n_chunks=0)
+        check(rx, data, n_chunks=4096, speculative=True)
+        check(rx, data, n_chunks=1000, force_global=True)
+
+
+def test_c3_over_cap_uses_speculative():
+    kws = W.c3_keywords(1)
+    rx = W.c3_regex(kws)
+    data = W.c3_input(6, 1 << 20, kws, rate=1e-5)
+    t = gpu_table(rx, False, 1000)
+    assert t.info["n_sfa"] == 0
+    with pytest.raises(sfa.SfaError):
+        run(rx, data, sfa_cap=1000)
+    check(rx, data, speculative=True, sfa_cap=1000)
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+EDGE_RX = ["(ab)*", W.REGEX_C1, W.REGEX_C2, ".*\\xff.*", "[\\x80-\\xff]*", "(.{3})*x?"]
+
+
+@pytest.mark.parametrize("rx", EDGE_RX)
+def test_edge_lengths_and_chunk_counts(rx):
+    rng = np.random.default_rng(abs(hash(rx)) % 1000)
+    for n in [0, 1, 2, 15, 16, 17, 255, 4095, 4096, 4097, 65537]:
+        data = rng.integers(0, 256, size=n, dtype=np.uint8)
+        if rx in ("(ab)*", W.REGEX_C2):
+            data = np.frombuffer((b"ab" * (n // 2 + 1))[:n], dtype=np.uint8).copy()
+        for p in [0, 1, 2, 3, 255, 256, 257, n + 5]:
+            if p > 1 << 20:
+                continue
+            check(rx, data, n_chunks=p)
+        check(rx, data, n_chunks=3, speculative=True)
+
+
+@pytest.mark.parametrize("offset", range(1, 16))
+def test_unaligned_base(offset):
+    data = W.c2_input(offset, n=100_003)
+    check(W.REGEX_C2, data, n_chunks=97, offset=offset)
+    check(W.REGEX_C2, data, n_chunks=97, offset=offset, speculative=True)
+    check(W.REGEX_C1, W.c1_input(offset, n=50_000), n_chunks=33, offset=offset)
+
+
+def test_all_byte_values_and_early_sink():
+    rng = np.random.default_rng(9)
+    data = rng.integers(0, 256, size=1 << 20, dtype=np.uint8)
+    for rx in [".*\\x00\\xff.*", "[^\\x7f]*", W.REGEX_C1, "(\\d|\\s|\\w)*"]:
+        check(rx, data, n_chunks=512)
+        check(rx, data, n_chunks=512, speculative=True)
+
+
+def test_forced_global_table_and_lds_table_agree():
+    data = W.c2_input(11, n=3_000_001)
+    a = check(W.REGEX_C2, data, n_chunks=2048, force_global=True)
+    b = check(W.REGEX_C2, data, n_chunks=2048)
+    assert a == b
+    assert gpu_table(W.REGEX_C2, True).info["table_in_lds"] == 0
+    assert gpu_table(W.REGEX_C2, False).info["table_in_lds"] == 1
+
+
+def test_rn_and_all_a_text():
+    rx = W.ra_regex(20)
+    data = np.full(1 << 22, ord("a"), dtype=np.uint8)
+    check(rx, data)
+    check(W.rn_regex(20), (np.arange(1 << 20) // 20 % 2 * 5 + 48 + np.arange(1 << 20) % 5).astype(np.uint8))
+
+
+def test_workspace_reuse_across_sizes():
+    t = gpu_table(W.REGEX_C1)
+    for seed, n in [(1, 1_000_000), (2, 1000), (3, 500_000), (4, 0), (5, 10)]:
+        data = W.c1_input(seed, n=n)
+        assert run(W.REGEX_C1, data, n_chunks=0) == oracle_result(W.REGEX_C1, data)

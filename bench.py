@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--speculative-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device-to-device copy of the workload size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -91,6 +93,15 @@ def main():
     import paper_1405_0562_amd as sfa
 
     wl = WORKLOADS[args.workload]
+    if args.calibrate_copy:
+        dev = torch.device("cuda", 0)
+        src = torch.empty(wl["n"], dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": wl["n"], "launches": args.steps}))
+        return
     rx, host = make_input(args.workload, args.seed)
     n = host.size
     dev = torch.device("cuda", 0)

@@ -164,6 +164,8 @@ typedef struct sfa_table_info {
     uint32_t map_bytes;      /* width of a mapping entry: 1, 2 or 4 */
     uint32_t table_in_lds;   /* 1 if the walk table is staged into LDS */
     uint32_t has_monoid;     /* 1 if the D-SFA product table mul[a][b] is present */
+    uint32_t strides;        /* bit s set: stride-s LDS walk tables are present (s = 1, 2, 4) */
+    uint32_t reserved;
     uint64_t device_bytes;   /* bytes used in d_buf */
 } sfa_table_info;
 
@@ -194,6 +196,32 @@ sfa_status sfa_match_workspace_bytes(const sfa_table *t, uint64_t n, uint32_t n_
                                      size_t *out_bytes);
 sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
                      void *d_ws, size_t ws_bytes, sfa_result *d_out, void *stream);
+
+/* Launch plan of the walk (every field 0 = library choice).  None of them
+ * changes the result (any division of the input is valid, Theorem 2).
+ *   stride      bytes consumed per transition-table lookup: 1, 2 or 4.  With
+ *               2 or 4 the table is the D-SFA transition over 2- or 4-byte
+ *               words, delta_s applied 2 or 4 times, indexed through a
+ *               65,536-entry table of byte-pair classes; available when the
+ *               table fits the LDS budget (sfa_table_info.strides).
+ *   pieces      K: interleaved pieces each chunk is walked as (1, 2, 4, 8).
+ *   load_bytes  G: bytes of one piece loaded per step (16, 32, 64, 128).
+ *   depth       D: load steps in flight per piece (loads for step j + D - 1
+ *               are issued before step j is walked).
+ * Supported (K, G, D): (1,64,2) (1,64,4) (1,128,2) (1,128,3) (1,128,4)
+ * (2,32,4) (2,64,2) (2,64,3) (2,64,4) (2,128,2) (4,32,2) (4,32,4) (4,64,2)
+ * (8,16,2) (8,32,2); tables in global memory use K in {1,2,4,8} only.
+ * Other values give SFA_ERR_INVALID_ARG. */
+typedef struct sfa_plan {
+    uint32_t stride;
+    uint32_t pieces;
+    uint32_t load_bytes;
+    uint32_t depth;
+} sfa_plan;
+
+sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
+                        const sfa_plan *plan, void *d_ws, size_t ws_bytes, sfa_result *d_out,
+                        void *stream);
 
 /* Speculative parallel DFA (Algorithm 3, Section 3): per chunk, every DFA
  * state is simulated as a possible start (|Q| lookups per byte), giving the

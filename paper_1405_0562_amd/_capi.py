@@ -55,7 +55,13 @@ class TableInfo(ctypes.Structure):
     _fields_ = [("n_dfa", ctypes.c_uint32), ("n_sfa", ctypes.c_uint32), ("n_classes", ctypes.c_uint32),
                 ("q0", ctypes.c_uint32), ("next_bytes", ctypes.c_uint32), ("map_bytes", ctypes.c_uint32),
                 ("table_in_lds", ctypes.c_uint32), ("has_monoid", ctypes.c_uint32),
+                ("strides", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("device_bytes", ctypes.c_uint64)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("stride", ctypes.c_uint32), ("pieces", ctypes.c_uint32), ("load_bytes", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32)]
 
 
 _P = ctypes.c_void_p
@@ -81,6 +87,7 @@ SIGNATURES = {
     "sfa_match_workspace_bytes": (ctypes.c_int, [_P, _U64, _U32, ctypes.POINTER(_SZ)]),
     "sfa_match": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _SZ, _P, _P]),
     "sfa_match_speculative": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _SZ, _P, _P]),
+    "sfa_match_ex": (ctypes.c_int, [_P, _P, _U64, _U32, ctypes.POINTER(Plan), _P, _SZ, _P, _P]),
 }
 
 _lib = None

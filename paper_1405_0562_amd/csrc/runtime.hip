@@ -55,27 +55,49 @@ extern "C" const char *sfa_status_string(sfa_status s) {
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr uint32_t kBlock = 256;          // threads per block of the walk kernel
-constexpr uint32_t kSpecWaves = 4;        // waves (chunks) per speculative block
+constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
+constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
 constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
 constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
-constexpr uint64_t kWsHeader = 256;       // control word area at the start of a workspace
+constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K <= 8)
+constexpr uint32_t kPairTable = 65536;       // byte-pair class table entries (u8)
+constexpr uint64_t kWsHeader = 256;          // control word area at the start of a workspace
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// A stride-S walk image, copied as one block into LDS by the walk kernel:
+//   [pair-class table u8[65536] (S >= 2)] [byte-class table u8[256]]
+//   [rows: n_sfa x (C^S (+ C if S >= 2)) u16 entries]
+// Class and pair-class entries hold column offsets in bytes (2 * index).
+// Entry values are row offsets in bytes (state id * row bytes), so one
+// transition is a single LDS load at (current row offset + column * 2).
+// Columns 0..C^S-1 hold delta_s applied to an S-byte word whose class digits
+// c_0..c_{S-1} (first byte most significant, base C) form the column index;
+// for S >= 2 the last C columns hold the single-byte transition (used for
+// unaligned heads and short tails).
+struct Image {
+    uint32_t present = 0;
+    uint32_t bytes = 0;       // total image bytes
+    uint32_t row_bytes = 0;   // RS
+    uint32_t one_off = 0;     // byte offset of the single-byte columns in a row
+    uint64_t off = 0;         // offset in the device buffer
+};
 
 struct Layout {
     uint32_t n_dfa = 0, n_sfa = 0, C = 0, q0 = 0;
     uint32_t next_w = 0, map_w = 0;
-    uint32_t in_lds = 0;
-    uint64_t off_cls = 0;    // u16[256]: cls[b] * next_w      (walk kernel)
-    uint64_t off_dcls = 0;   // u16[256]: cls[b] * 2            (speculative kernel)
+    uint64_t off_cls = 0;    // u16[256]: cls[b] * next_w   (global-table walk)
+    uint64_t off_dcls = 0;   // u16[256]: cls[b] * 2        (speculative kernel)
     uint64_t off_acc = 0;    // u8[n_dfa]
     uint64_t off_dnext = 0;  // u16[n_dfa * C]
-    uint64_t off_next = 0;   // next_w bytes [n_sfa * C]
+    uint64_t off_next = 0;   // next_w bytes [n_sfa * C]: state ids (global-table walk)
     uint64_t off_map = 0;    // map_w bytes [n_sfa * n_dfa]
+    Image img[3];            // strides 1, 2, 4
     uint64_t total = 0;
-    uint32_t next_bytes = 0;  // bytes of the walk table
+    uint64_t next_bytes = 0;
 };
+
+inline int stride_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : -1; }
 
 }  // namespace
 
@@ -131,7 +153,16 @@ sfa_status validate(const sfa_table_desc *d) {
     return SFA_OK;
 }
 
-Layout plan(const sfa_table_desc *d, const sfa_load_options *o) {
+uint64_t ipow(uint64_t b, uint32_t e) {
+    uint64_t r = 1;
+    while (e--) r *= b;
+    return r;
+}
+
+// LDS bytes the walk kernel needs besides the image: piece states + scratch.
+constexpr uint32_t kWalkExtraLds = kMaxIds * 4 + 16 + kScratchLds;
+
+Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_limit) {
     Layout L;
     L.n_dfa = d->n_dfa;
     L.n_sfa = d->n_sfa;
@@ -150,13 +181,32 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o) {
     L.off_dnext = off;
     off = align256(off + 2ull * d->n_dfa * d->n_classes);
     L.off_next = off;
-    L.next_bytes = (uint32_t)std::min<uint64_t>(UINT32_MAX, (uint64_t)L.next_w * d->n_sfa * d->n_classes);
-    off = align256(off + (uint64_t)L.next_w * d->n_sfa * d->n_classes);
+    L.next_bytes = (uint64_t)L.next_w * d->n_sfa * d->n_classes;
+    off = align256(off + L.next_bytes);
     L.off_map = off;
     off = align256(off + (uint64_t)L.map_w * d->n_sfa * d->n_dfa);
+    const bool allow_lds = d->n_sfa && !(o && o->force_global);
+    const uint64_t budget = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : kDefaultLdsBudget + kPairTable,
+                                               lds_limit > kWalkExtraLds ? lds_limit - kWalkExtraLds : 0);
+    for (uint32_t S : {1u, 2u, 4u}) {
+        Image &im = L.img[stride_index(S)];
+        if (!allow_lds) continue;
+        if (S >= 2 && 2 * ((uint64_t)L.C * L.C - 1) > 255) continue;   // doubled pair index fits u8
+        if (S == 1 && 2 * ((uint64_t)L.C - 1) > 255) continue;
+        const uint64_t cs = ipow(L.C, S);
+        const uint64_t cols = cs + (S >= 2 ? L.C : 0);
+        const uint64_t rs = 2 * cols;
+        if ((uint64_t)d->n_sfa * rs > 65536) continue;   // row offsets must fit u16
+        const uint64_t bytes = (S >= 2 ? kPairTable : 0) + 256 + (uint64_t)d->n_sfa * rs;
+        if (bytes > budget) continue;
+        im.present = 1;
+        im.bytes = (uint32_t)bytes;
+        im.row_bytes = (uint32_t)rs;
+        im.one_off = S >= 2 ? (uint32_t)(2 * cs) : 0;
+        im.off = off;
+        off = align256(off + bytes);
+    }
     L.total = off;
-    uint32_t budget = (o && o->lds_budget) ? o->lds_budget : kDefaultLdsBudget;
-    L.in_lds = (d->n_sfa && !(o && o->force_global) && (uint64_t)L.next_bytes <= budget) ? 1 : 0;
     return L;
 }
 
@@ -167,14 +217,15 @@ void put(std::vector<uint8_t> &img, uint64_t off, uint64_t i, T v) {
 
 void pack(const sfa_table_desc *d, const Layout &L, std::vector<uint8_t> &img) {
     img.assign(L.total, 0);
+    const uint32_t C = L.C;
     for (int b = 0; b < 256; ++b) {
         put<uint16_t>(img, L.off_cls, b, (uint16_t)(d->byte_class[b] * L.next_w));
         put<uint16_t>(img, L.off_dcls, b, (uint16_t)(d->byte_class[b] * 2));
     }
     for (uint32_t q = 0; q < d->n_dfa; ++q) img[L.off_acc + q] = d->dfa_accept[q] ? 1 : 0;
-    for (uint64_t i = 0; i < (uint64_t)d->n_dfa * d->n_classes; ++i)
+    for (uint64_t i = 0; i < (uint64_t)d->n_dfa * C; ++i)
         put<uint16_t>(img, L.off_dnext, i, (uint16_t)d->dfa_next[i]);
-    for (uint64_t i = 0; i < (uint64_t)d->n_sfa * d->n_classes; ++i) {
+    for (uint64_t i = 0; i < (uint64_t)d->n_sfa * C; ++i) {
         uint32_t v = d->sfa_next[i];
         if (L.next_w == 1) put<uint8_t>(img, L.off_next, i, (uint8_t)v);
         else if (L.next_w == 2) put<uint16_t>(img, L.off_next, i, (uint16_t)v);
@@ -185,6 +236,36 @@ void pack(const sfa_table_desc *d, const Layout &L, std::vector<uint8_t> &img) {
         if (L.map_w == 1) put<uint8_t>(img, L.off_map, i, (uint8_t)v);
         else put<uint16_t>(img, L.off_map, i, (uint16_t)v);
     }
+    for (uint32_t S : {1u, 2u, 4u}) {
+        const Image &im = L.img[stride_index(S)];
+        if (!im.present) continue;
+        uint64_t o = im.off;
+        if (S >= 2) {
+            for (uint32_t h = 0; h < kPairTable; ++h)   // little endian: low byte comes first in the text
+                img[o + h] = (uint8_t)(2 * (d->byte_class[h & 255] * C + d->byte_class[h >> 8]));
+            o += kPairTable;
+        }
+        for (int b = 0; b < 256; ++b) img[o + b] = (uint8_t)(2 * d->byte_class[b]);
+        o += 256;
+        const uint32_t cs = (uint32_t)ipow(C, S);
+        const uint32_t cols = im.row_bytes / 2;
+        for (uint32_t s = 0; s < d->n_sfa; ++s) {
+            for (uint32_t col = 0; col < cs; ++col) {
+                uint32_t t = s, rem = col, div = cs / C;
+                for (uint32_t i = 0; i < S; ++i) {      // digits, most significant first
+                    const uint32_t c = rem / div;
+                    rem -= c * div;
+                    div = div > 1 ? div / C : 1;
+                    t = d->sfa_next[(uint64_t)t * C + c];
+                }
+                put<uint16_t>(img, o, (uint64_t)s * cols + col, (uint16_t)(t * im.row_bytes));
+            }
+            if (S >= 2)
+                for (uint32_t c = 0; c < C; ++c)
+                    put<uint16_t>(img, o, (uint64_t)s * cols + cs + c,
+                                  (uint16_t)(d->sfa_next[(uint64_t)s * C + c] * im.row_bytes));
+        }
+    }
 }
 
 }  // namespace
@@ -194,7 +275,9 @@ extern "C" sfa_status sfa_table_device_bytes(const sfa_table_desc *desc, const s
     if (!out_bytes) return sfa_fail(SFA_ERR_INVALID_ARG, "null out_bytes");
     sfa_status st = validate(desc);
     if (st != SFA_OK) return st;
-    *out_bytes = (size_t)plan(desc, opts).total;
+    // the LDS limit of gfx950 (160 KiB per workgroup); the loader re-plans
+    // with the device's reported limit, which can only shrink the layout
+    *out_bytes = (size_t)plan(desc, opts, 160 * 1024).total;
     return SFA_OK;
 }
 
@@ -206,12 +289,12 @@ extern "C" sfa_status sfa_load_table(const sfa_table_desc *desc, const sfa_load_
     if (st != SFA_OK) return st;
     if (!d_buf) return sfa_fail(SFA_ERR_INVALID_ARG, "null device buffer");
     if (((uintptr_t)d_buf & 255) != 0) return sfa_fail(SFA_ERR_INVALID_ARG, "device buffer must be 256-byte aligned");
-    Layout L = plan(desc, opts);
-    if (d_bytes < L.total) return sfa_fail(SFA_ERR_BUFFER_TOO_SMALL, "table buffer smaller than sfa_table_device_bytes");
     int dev;
     uint32_t lds, cus;
     st = check_device(dev, lds, cus);
     if (st != SFA_OK) return st;
+    Layout L = plan(desc, opts, std::min<uint32_t>(lds, 160 * 1024));
+    if (d_bytes < L.total) return sfa_fail(SFA_ERR_BUFFER_TOO_SMALL, "table buffer smaller than sfa_table_device_bytes");
     sfa_table *t = new (std::nothrow) sfa_table();
     if (!t) return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
     try {
@@ -220,7 +303,6 @@ extern "C" sfa_status sfa_load_table(const sfa_table_desc *desc, const sfa_load_
         delete t;
         return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
     }
-    if (L.in_lds && L.next_bytes + 512 + kScratchLds + 8 * kBlock * 4 > lds) L.in_lds = 0;
     t->L = L;
     t->d_base = (uint8_t *)d_buf;
     t->device = dev;
@@ -237,14 +319,16 @@ extern "C" sfa_status sfa_load_table(const sfa_table_desc *desc, const sfa_load_
 
 extern "C" sfa_status sfa_table_get_info(const sfa_table *t, sfa_table_info *out) {
     if (!t || !out) return sfa_fail(SFA_ERR_INVALID_ARG, "null argument");
+    std::memset(out, 0, sizeof(*out));
     out->n_dfa = t->L.n_dfa;
     out->n_sfa = t->L.n_sfa;
     out->n_classes = t->L.C;
     out->q0 = t->L.q0;
     out->next_bytes = t->L.next_w;
     out->map_bytes = t->L.map_w;
-    out->table_in_lds = t->L.in_lds;
+    out->table_in_lds = t->L.img[0].present | t->L.img[1].present | t->L.img[2].present;
     out->has_monoid = 0;
+    out->strides = (t->L.img[0].present ? 2u : 0u) | (t->L.img[1].present ? 4u : 0u) | (t->L.img[2].present ? 16u : 0u);
     out->device_bytes = t->L.total;
     return SFA_OK;
 }
@@ -266,12 +350,18 @@ struct MatchArgs {
     uint32_t n_chunks;
     uint32_t n_dfa;
     uint32_t q0;
-    uint32_t row_bytes;      // C * next_w (walk) or C * 2 (speculative)
-    uint32_t next_bytes;     // bytes of the walk table (staged into LDS when in_lds)
+    uint32_t row_bytes;      // bytes per table row
+    uint32_t one_off;        // LDS walk: byte offset of the single-byte columns
+    uint32_t wide_mul;       // LDS walk, stride 4: C*C (first pair's weight in the column index)
+    uint32_t img_bytes;      // LDS walk: image bytes; speculative: DFA table bytes
     uint32_t groups;         // G: groups per block in the block composition
     uint32_t final_groups;   // G for the grid composition
-    const uint16_t *cls;     // u16[256]
-    const uint8_t *next;     // walk table (or u16 dfa table for speculative)
+    uint32_t region_bytes;   // LDS bytes at offset 0 free once the walk is over (multiple of 16)
+    uint32_t map_lds;        // 1: the mapping rows are copied into that region for the block composition
+    uint32_t map_bytes;      // bytes of the mapping rows
+    uint32_t bm_lds;         // 1: the last block stages all block mappings (u16) in LDS
+    const uint16_t *cls;     // global walk / speculative: u16[256] class column offsets
+    const uint8_t *img;      // LDS image, global walk table, or u16 DFA table
     const uint8_t *map;      // mapping rows
     const uint8_t *accept;   // u8[n_dfa]
     uint32_t *counter;       // workspace control word
@@ -279,210 +369,403 @@ struct MatchArgs {
     sfa_result *out;
 };
 
-template <typename MT>
-__device__ __forceinline__ uint32_t map_at(const uint8_t *__restrict__ map, uint32_t f, uint32_t n_dfa, uint32_t q) {
-    return ((const MT *)map)[(size_t)f * n_dfa + q];
+// Phase 1 of a composition: the elements 0..E-1 (mappings, in text order) are
+// cut into G groups of R consecutive elements; for every (group g, start
+// state q) pair, q is followed through the group's mappings, the earlier
+// mapping first (reverse composition, f . g = g o f), and the end state is
+// stored at out[g * n + q].  `get(e, x)` is mapping e applied to x.  Four
+// pairs per thread are followed together to hide load latency.
+template <typename Get>
+__device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, uint32_t G, uint32_t n,
+                                              uint32_t *out) {
+    const uint32_t items = G * n;
+    for (uint32_t base = threadIdx.x; base < items; base += 4 * blockDim.x) {
+        uint32_t it[4], x[4], e0[4], e1[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            it[i] = min(base + (uint32_t)i * blockDim.x, items - 1);
+            const uint32_t g = it[i] / n;
+            x[i] = it[i] - g * n;
+            e0[i] = g * R;
+            e1[i] = min(E, e0[i] + R);
+        }
+        for (uint32_t r = 0; r < R; ++r) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t e = e0[i] + r;
+                const uint32_t y = get(min(e, E - 1), x[i]);
+                x[i] = e < e1[i] ? y : x[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (base + (uint32_t)i * blockDim.x < items) out[it[i]] = x[i];
+    }
 }
 
-// Composition of E element mappings given as rows of `map` (element e is
-// D-SFA state ids[e]), in text order, into the block mapping M[q] (q < n_dfa):
-//   phase 1: the E elements are cut into G consecutive groups; for every
-//            (group, start state) pair one thread follows the start state
-//            through the group's mappings (reverse composition applies the
-//            earlier mapping first);
-//   phase 2: every start state is followed through the G group mappings.
+// Block composition: the block's E piece states (D-SFA ids in text order,
+// s_ids) become the block mapping M[q], written to out_map.  The mapping rows
+// are read from LDS (copied over the walk-table region) when they fit.
 template <typename MT>
-__device__ void compose_block(const uint32_t *ids, uint32_t E, const uint8_t *__restrict__ map, uint32_t n_dfa,
-                              uint32_t G, uint32_t *scratch, uint32_t *__restrict__ out_map) {
-    const uint32_t R = E / G;
-    const uint32_t items = G * n_dfa;
-    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-        const uint32_t g = it / n_dfa, q = it - g * n_dfa;
-        uint32_t x = q;
-        const uint32_t *e = ids + g * R;
-        for (uint32_t i = 0; i < R; ++i) x = map_at<MT>(map, e[i], n_dfa, x);
-        if (G == 1)
-            out_map[q] = x;
-        else
-            scratch[it] = x;
+__device__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t *s_ids, uint32_t E,
+                              uint32_t *scratch, uint32_t *__restrict__ out_map) {
+    const uint32_t n = a.n_dfa, G = a.groups, R = E / G;
+    uint32_t *target = G == 1 ? nullptr : scratch;
+    if (a.map_lds) {
+        {
+            const uint4 *src = (const uint4 *)a.map;
+            uint4 *dst = (uint4 *)smem;
+            for (uint32_t i = threadIdx.x; i < (a.map_bytes + 15) / 16; i += blockDim.x) dst[i] = src[i];
+        }
+        __syncthreads();
+        const MT *m = (const MT *)smem;
+        auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[s_ids[e] * n + x]; };
+        if (G == 1) {
+            follow_groups(get, E, R, 1, n, out_map);
+            return;
+        }
+        follow_groups(get, E, R, G, n, target);
+    } else {
+        const MT *__restrict__ m = (const MT *)a.map;
+        auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[(size_t)s_ids[e] * n + x]; };
+        if (G == 1) {
+            follow_groups(get, E, R, 1, n, out_map);
+            return;
+        }
+        follow_groups(get, E, R, G, n, target);
     }
-    if (G == 1) return;
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < n_dfa; q += blockDim.x) {
+    // phase 2: every start state through the G group mappings
+    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
         uint32_t x = q;
-        for (uint32_t g = 0; g < G; ++g) x = scratch[g * n_dfa + x];
+        for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
         out_map[q] = x;
     }
 }
 
 // Grid-level step run by the last block to finish: composes the block
 // mappings in block order, applies the result to q0 and writes the answer.
-__device__ void finalize_grid(const MatchArgs &a, uint32_t *scratch) {
+__device__ void finalize_grid(const MatchArgs &a, uint8_t *smem, uint32_t *scratch) {
     const uint32_t B = gridDim.x, n = a.n_dfa;
     const uint32_t G = a.final_groups;   // groups of consecutive blocks
     const uint32_t R = (B + G - 1) / G;
     const uint32_t *bm = a.block_maps;
-    if (G == 1) {
-        if (threadIdx.x == 0) {
-            uint32_t x = a.q0;
-            for (uint32_t b = 0; b < B; ++b) x = __builtin_nontemporal_load(&bm[(size_t)b * n + x]);
-            a.out->state = x;
-            a.out->accept = a.accept[x];
+    uint32_t x = a.q0;
+    if (a.bm_lds) {
+        uint16_t *s_bm = (uint16_t *)smem;
+        for (uint32_t i = threadIdx.x; i < B * n; i += blockDim.x) s_bm[i] = (uint16_t)bm[i];
+        __syncthreads();
+        if (G == 1) {
+            if (threadIdx.x == 0)
+                for (uint32_t b = 0; b < B; ++b) x = s_bm[b * n + x];
+        } else {
+            follow_groups([&](uint32_t b, uint32_t y) -> uint32_t { return s_bm[b * n + y]; }, B, R, G, n, scratch);
         }
-        return;
-    }
-    const uint32_t items = G * n;
-    for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
-        const uint32_t g = it / n, q = it - g * n;
-        uint32_t x = q;
-        if (g > 0 || q == a.q0) {
-            const uint32_t b0 = g * R, b1 = min(B, b0 + R);
-            for (uint32_t b = b0; b < b1; ++b) x = __builtin_nontemporal_load(&bm[(size_t)b * n + x]);
+    } else {
+        if (G == 1) {
+            if (threadIdx.x == 0)
+                for (uint32_t b = 0; b < B; ++b) x = bm[(size_t)b * n + x];
+        } else {
+            follow_groups([&](uint32_t b, uint32_t y) -> uint32_t { return bm[(size_t)b * n + y]; }, B, R, G, n,
+                          scratch);
         }
-        scratch[it] = x;
     }
-    __syncthreads();
+    if (G > 1) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
+    }
     if (threadIdx.x == 0) {
-        uint32_t x = a.q0;
-        for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
         a.out->state = x;
         a.out->accept = a.accept[x];
     }
 }
 
 // Publish this block's mapping and let the last block compose the grid.
-__device__ void block_done(const MatchArgs &a, uint32_t *scratch) {
-    __shared__ uint32_t s_last;
+// s_last is one LDS word used for nothing else.
+__device__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, uint32_t *s_last) {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         // wraps to 0 after gridDim.x increments, leaving the word zero again
         const uint32_t prev = atomicInc(a.counter, gridDim.x - 1);
-        s_last = (prev == gridDim.x - 1) ? 1u : 0u;
+        *s_last = (prev == gridDim.x - 1) ? 1u : 0u;
     }
     __syncthreads();
-    if (!s_last) return;
+    if (!*s_last) return;
     __threadfence();
-    finalize_grid(a, scratch);
+    finalize_grid(a, smem, scratch);
 }
 
-__device__ __forceinline__ uint32_t byte_of(const uint4 &v, int i) {
-    const uint32_t w = i < 4 ? v.x : i < 8 ? v.y : i < 12 ? v.z : v.w;
-    return (w >> (8 * (i & 3))) & 0xffu;
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int d) {
+    return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
 }
 
-// Walk kernel.  Lane l of block b owns chunk c = b*256 + l, walked from the
-// identity (state 0) as K consecutive pieces in lock step; the K*256 piece
-// states of the block are composed in text order, then across blocks.
-template <int K, typename NT, typename MT, bool LDS>
-__global__ __launch_bounds__(kBlock) void k_sfa_walk(MatchArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint16_t *s_cls = (uint16_t *)smem;                       // 512 B
-    uint8_t *s_tab = smem + 512;                              // walk table when LDS
-    const uint32_t tab_lds = LDS ? ((a.next_bytes + 15) & ~15u) : 0;
-    uint32_t *s_ids = (uint32_t *)(smem + 512 + tab_lds);     // K*256 piece states
-    uint32_t *s_scr = s_ids + K * kBlock;                     // composition scratch
-
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) s_cls[i] = a.cls[i];
-    if constexpr (LDS) {
-        const uint4 *src = (const uint4 *)a.next;
-        uint4 *dst = (uint4 *)s_tab;
-        for (uint32_t i = threadIdx.x; i < tab_lds / 16; i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
-
-    const uint32_t rb = a.row_bytes;
+// Chunk bounds of this lane and the split of the chunk into K pieces whose
+// lengths are multiples of Q (so every piece starts at the same alignment).
+template <int K, int Q>
+__device__ __forceinline__ void lane_pieces(const MatchArgs &a, uint64_t &c0, uint64_t &c1, uint64_t *pos,
+                                            uint64_t *end) {
     const uint64_t chunk = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    uint64_t c0 = a.n, c1 = a.n;
+    c0 = a.n;
+    c1 = a.n;
     if (chunk < a.n_chunks) {
         c0 = min(a.n, chunk * a.chunk_len);
         c1 = min(a.n, c0 + a.chunk_len);
     }
     const uint64_t len = c1 - c0;
-    const uint64_t piece = (((len + K - 1) / K) + 15) & ~uint64_t(15);
-
-    uint64_t pos[K], end[K];
-    uint32_t st[K];
+    const uint64_t piece = (((len + K - 1) / K) + Q - 1) / Q * Q;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         pos[k] = min(c1, c0 + k * piece);
         end[k] = min(c1, pos[k] + piece);
-        st[k] = 0;
     }
-    // one D-SFA transition: f <- delta_s[f, class(b)]
+}
+
+// LDS walk kernel, stride S (bytes per transition lookup), K pieces per lane,
+// G bytes of each piece loaded per step, loads issued D - 1 steps ahead.  Lane l of block b owns chunk
+// c = b*256 + l; its K piece states (in text order) join the block
+// composition, then the grid composition.
+template <int S, int K, int G, int D>
+__global__ __launch_bounds__(kBlock) void k_sfa_lds(MatchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    constexpr uint32_t CLS = (S >= 2) ? kPairTable : 0u;   // byte-class table
+    constexpr uint32_t TAB = CLS + 256;                     // rows
+    const uint32_t img = (a.img_bytes + 15) & ~15u;
+    uint32_t *s_ids = (uint32_t *)(smem + img);
+    uint32_t *s_flag = s_ids + K * kBlock;
+    uint32_t *s_scr = s_flag + 4;
+    {
+        const uint4 *src = (const uint4 *)a.img;
+        uint4 *dst = (uint4 *)smem;
+        for (uint32_t i = threadIdx.x; i < img / 16; i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const uint32_t one = a.one_off, wide = a.wide_mul;
+    auto row = [&](uint32_t off) -> uint32_t { return *(const uint16_t *)(smem + TAB + off); };
+    // one byte: f <- delta_s[f, class(b)]
+    auto step1 = [&](uint32_t st, uint32_t b) -> uint32_t { return row(st + one + smem[CLS + b]); };
+
+    uint64_t c0, c1, pos[K], end[K];
+    lane_pieces<K, G>(a, c0, c1, pos, end);
+    uint32_t st[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) st[k] = 0;     // f_I
+
+    if (c1 > c0) {
+        // head: single bytes up to 16-byte alignment (the same for all pieces)
+        const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + c0) & 15)) & 15);
+        for (uint32_t i = 0; i < head; ++i) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool act = pos[k] < end[k];
+                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
+                st[k] = act ? t : st[k];
+                pos[k] += act ? 1 : 0;
+            }
+        }
+        // body: G-byte groups (16-byte aligned loads), next group loaded first
+        uint64_t nb[K], maxnb = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            nb[k] = (end[k] - pos[k]) / G;
+            maxnb = max(maxnb, nb[k]);
+        }
+        if (maxnb) {
+            // ring of D load buffers: the loads of step j + D - 1 are issued
+            // before step j is walked
+            constexpr int V = G / 16;
+            uint4 buf[D][K][V];
+            auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint64_t base = (step < nb[k]) ? pos[k] + (uint64_t)G * step : pos[0];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
+                }
+            };
+            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
+                uint32_t t[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) t[k] = st[k];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        if constexpr (S == 1) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                uint32_t c[K];
+#pragma unroll
+                                for (int k = 0; k < K; ++k) c[k] = smem[CLS + ((word_of(cur[k][v], d) >> (8 * i)) & 255u)];
+#pragma unroll
+                                for (int k = 0; k < K; ++k) t[k] = row(t[k] + c[k]);
+                            }
+                        } else if constexpr (S == 2) {
+                            uint32_t p0[K], p1[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                const uint32_t w = word_of(cur[k][v], d);
+                                p0[k] = smem[w & 0xffffu];
+                                p1[k] = smem[w >> 16];
+                            }
+#pragma unroll
+                            for (int k = 0; k < K; ++k) t[k] = row(t[k] + p0[k]);
+#pragma unroll
+                            for (int k = 0; k < K; ++k) t[k] = row(t[k] + p1[k]);
+                        } else {
+                            uint32_t p0[K], p1[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                const uint32_t w = word_of(cur[k][v], d);
+                                p0[k] = smem[w & 0xffffu];
+                                p1[k] = smem[w >> 16];
+                            }
+#pragma unroll
+                            for (int k = 0; k < K; ++k) t[k] = row(__umul24(p0[k], wide) + p1[k] + t[k]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) st[k] = (step < nb[k]) ? t[k] : st[k];
+            };
+#pragma unroll
+            for (int d = 0; d < D - 1; ++d)
+                if ((uint64_t)d < maxnb) issue(buf[d], d);
+            uint64_t j = 0;
+            // steady state: every issued step exists, no bounds checks
+            for (; j + 2 * D - 1 <= maxnb; j += D) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    issue(buf[(d + D - 1) % D], j + d + D - 1);
+                    walk(buf[d], j + d);
+                }
+            }
+            // last steps
+            for (; j < maxnb; j += D) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (j + d < maxnb) {
+                        if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
+                        walk(buf[d], j + d);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) pos[k] += (uint64_t)G * nb[k];
+        }
+        // tail: fewer than G bytes per piece
+        uint32_t maxtail = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
+        for (uint32_t i = 0; i < maxtail; ++i) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool act = pos[k] < end[k];
+                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
+                st[k] = act ? t : st[k];
+                pos[k] += act ? 1 : 0;
+            }
+        }
+    }
+    const uint32_t rs = a.row_bytes;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k] / rs;
+    __syncthreads();   // the walk is over: the image region may be reused
+    const uint32_t E = K * kBlock;
+    uint32_t *bmap = a.block_maps + (size_t)blockIdx.x * a.n_dfa;
+    if (a.n_dfa <= 256)
+        compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
+    else
+        compose_block<uint16_t>(a, smem, s_ids, E, s_scr, bmap);
+    block_done(a, smem, s_scr, s_flag);
+}
+
+// Global-table walk (tables too large for LDS): stride 1, state ids of
+// width NT, table rows read through L1/L2.
+template <int K, typename NT>
+__global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint16_t *s_cls = (uint16_t *)smem;            // 512 B
+    uint32_t *s_ids = (uint32_t *)(smem + 512);
+    uint32_t *s_flag = s_ids + K * kBlock;
+    uint32_t *s_scr = s_flag + 4;
+    for (uint32_t i = threadIdx.x; i < 256; i += kBlock) s_cls[i] = a.cls[i];
+    __syncthreads();
+    const uint32_t rb = a.row_bytes;
+    const uint8_t *__restrict__ tab = a.img;
     auto step = [&](uint32_t s, uint32_t b) -> uint32_t {
-        if constexpr (LDS)
-            return *(const NT *)(s_tab + s * rb + s_cls[b]);
-        else
-            return *(const NT *)(a.next + (size_t)s * rb + s_cls[b]);
+        return *(const NT *)(tab + (size_t)__umul24(s, rb) + s_cls[b]);
     };
-    if (len > 0) {
-    // head: single bytes up to 16-byte alignment (same for all pieces)
-    const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + c0) & 15)) & 15);
-    for (uint32_t i = 0; i < head; ++i) {
+    uint64_t c0, c1, pos[K], end[K];
+    lane_pieces<K, 16>(a, c0, c1, pos, end);
+    uint32_t st[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool act = pos[k] < end[k];
-            const uint32_t b = a.in[act ? pos[k] : c0];
-            const uint32_t t = step(st[k], b);
-            st[k] = act ? t : st[k];
-            pos[k] += act ? 1 : 0;
-        }
-    }
-    // body: aligned 16-byte groups, next group loaded before the current one is walked
-    uint64_t nb[K];
-    uint64_t maxnb = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        nb[k] = (end[k] - pos[k]) / 16;
-        maxnb = max(maxnb, nb[k]);
-    }
-    if (maxnb) {
-        uint4 cur[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) cur[k] = *(const uint4 *)(a.in + (nb[k] ? pos[k] : pos[0]));
-        for (uint64_t j = 0; j < maxnb; ++j) {
-            uint4 nxt[K];
+    for (int k = 0; k < K; ++k) st[k] = 0;
+    if (c1 > c0) {
+        const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + c0) & 15)) & 15);
+        for (uint32_t i = 0; i < head; ++i) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const bool more = j + 1 < nb[k];
-                nxt[k] = *(const uint4 *)(a.in + (more ? pos[k] + 16 * (j + 1) : pos[0]));
-            }
-            uint32_t t[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) t[k] = st[k];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) t[k] = step(t[k], byte_of(cur[k], i));
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                st[k] = (j < nb[k]) ? t[k] : st[k];
-                cur[k] = nxt[k];
+                const bool act = pos[k] < end[k];
+                const uint32_t t = step(st[k], a.in[act ? pos[k] : c0]);
+                st[k] = act ? t : st[k];
+                pos[k] += act ? 1 : 0;
             }
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k) pos[k] += 16 * nb[k];
-    }
-    // tail: fewer than 16 bytes per piece
-    for (uint32_t i = 0; i < 16; ++i) {
+        uint64_t nb[K], maxnb = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const bool act = pos[k] < end[k];
-            const uint32_t b = a.in[act ? pos[k] : c0];
-            const uint32_t t = step(st[k], b);
-            st[k] = act ? t : st[k];
-            pos[k] += act ? 1 : 0;
+            nb[k] = (end[k] - pos[k]) / 16;
+            maxnb = max(maxnb, nb[k]);
+        }
+        if (maxnb) {
+            uint4 cur[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) cur[k] = *(const uint4 *)(a.in + (nb[k] ? pos[k] : pos[0]));
+            for (uint64_t j = 0; j < maxnb; ++j) {
+                uint4 nxt[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    nxt[k] = *(const uint4 *)(a.in + ((j + 1 < nb[k]) ? pos[k] + 16 * (j + 1) : pos[0]));
+                uint32_t t[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) t[k] = st[k];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) t[k] = step(t[k], (word_of(cur[k], i >> 2) >> (8 * (i & 3))) & 255u);
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    st[k] = (j < nb[k]) ? t[k] : st[k];
+                    cur[k] = nxt[k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) pos[k] += 16 * nb[k];
+        }
+        for (uint32_t i = 0; i < 16; ++i) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool act = pos[k] < end[k];
+                const uint32_t t = step(st[k], a.in[act ? pos[k] : c0]);
+                st[k] = act ? t : st[k];
+                pos[k] += act ? 1 : 0;
+            }
         }
     }
-    }  // len > 0
 #pragma unroll
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k];
     __syncthreads();
-    compose_block<MT>(s_ids, K * kBlock, a.map, a.n_dfa, a.groups, s_scr,
-                      a.block_maps + (size_t)blockIdx.x * a.n_dfa);
-    block_done(a, s_scr);
+    const uint32_t E = K * kBlock;
+    uint32_t *bmap = a.block_maps + (size_t)blockIdx.x * a.n_dfa;
+    if (a.n_dfa <= 256)
+        compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
+    else
+        compose_block<uint16_t>(a, smem, s_ids, E, s_scr, bmap);
+    block_done(a, smem, s_scr, s_flag);
 }
 
 // Speculative kernel (Algorithm 3).  Wave w of block b walks chunk
@@ -493,11 +776,12 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint16_t *s_cls = (uint16_t *)smem;                        // 512 B
     uint16_t *s_dn = (uint16_t *)(smem + 512);                 // u16 [n_dfa * C]
-    const uint32_t dn_bytes = (a.next_bytes + 15) & ~15u;
-    uint32_t *s_T = (uint32_t *)(smem + 512 + dn_bytes);       // [4][n_dfa]
+    const uint32_t dn_bytes = (a.img_bytes + 15) & ~15u;
+    uint32_t *s_flag = (uint32_t *)(smem + 512 + dn_bytes);
+    uint32_t *s_T = s_flag + 4;                                // [4][n_dfa]
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) s_cls[i] = a.cls[i];
     {
-        const uint4 *src = (const uint4 *)a.next;
+        const uint4 *src = (const uint4 *)a.img;
         uint4 *dst = (uint4 *)s_dn;
         for (uint32_t i = threadIdx.x; i < dn_bytes / 16; i += blockDim.x) dst[i] = src[i];
     }
@@ -525,7 +809,7 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
         const uint4 v = *(const uint4 *)(a.in + p);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const uint32_t b = byte_of(v, i);
+            const uint32_t b = (word_of(v, i >> 2) >> (8 * (i & 3))) & 255u;
 #pragma unroll
             for (int s = 0; s < S; ++s) T[s] = step(T[s], b);
         }
@@ -547,27 +831,44 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
         for (uint32_t w = 0; w < kSpecWaves; ++w) x = s_T[w * n + x];
         bm[q] = x;
     }
-    block_done(a, s_T);
+    block_done(a, smem, s_T, s_flag);
 }
 
 // ---------------------------------------------------------------------------
 // host-side launch
 // ---------------------------------------------------------------------------
+// Supported (pieces K, load bytes G, prefetch depth D) shapes of the LDS walk.
+#define SFA_LDS_SHAPES(X) \
+    X(1, 64, 2) X(1, 64, 4) X(1, 128, 2) X(1, 128, 3) X(1, 128, 4) \
+    X(2, 32, 4) X(2, 64, 2) X(2, 64, 3) X(2, 64, 4) X(2, 128, 2) \
+    X(4, 32, 2) X(4, 32, 4) X(4, 64, 2) X(8, 16, 2) X(8, 32, 2)
+
+bool lds_shape_ok(uint32_t K, uint32_t G, uint32_t D) {
+#define SFA_SHAPE_OK(k, g, d) if (K == k && G == g && D == d) return true;
+    SFA_LDS_SHAPES(SFA_SHAPE_OK)
+#undef SFA_SHAPE_OK
+    return false;
+}
+
 struct Plan {
-    uint32_t n_chunks = 0, blocks = 0, K = 1, groups = 1, final_groups = 1;
+    uint32_t n_chunks = 0, blocks = 0, S = 0, K = 1, G = 16, D = 2, groups = 1, final_groups = 1;
     uint64_t chunk_len = 0;
     size_t ws_bytes = 0;
 };
 
-uint32_t pick_groups(uint32_t items_max, uint32_t n_dfa, uint32_t cap_groups) {
-    // largest power of two G <= cap_groups with G * n_dfa * 4 <= kScratchLds
+// Groups for a composition of E elements: about sqrt(E) groups, so that the
+// parallel phase (chains of E/G) and the serial phase (chains of G) balance,
+// within the LDS scratch and at most 4096 (group, state) pairs.
+uint32_t pick_groups(uint32_t E, uint32_t n_dfa) {
     uint32_t G = 1;
-    while (G * 2 <= cap_groups && (uint64_t)G * 2 * n_dfa * 4 <= kScratchLds && G * 2 <= items_max) G *= 2;
+    while ((uint64_t)(G * 2) * (G * 2) <= E && (uint64_t)G * 2 * n_dfa * 4 <= kScratchLds &&
+           (uint64_t)G * 2 * n_dfa <= 4096)
+        G *= 2;
     return G;
 }
 
-Plan make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool speculative) {
-    Plan P;
+sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool speculative, const sfa_plan *user,
+                     Plan &P) {
     const uint32_t per_block = speculative ? kSpecWaves : kBlock;
     if (n_chunks == 0) {
         const uint64_t target = speculative ? 4096 : 1024;   // bytes per chunk at least
@@ -580,49 +881,82 @@ Plan make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool speculati
     P.chunk_len = n ? (n + P.n_chunks - 1) / P.n_chunks : 0;
     P.blocks = (uint32_t)((P.n_chunks + per_block - 1) / per_block);
     if (!speculative) {
-        // pieces per lane: at least 256 bytes per piece
-        uint64_t k = P.chunk_len / 256;
-        P.K = k >= 8 ? 8 : k >= 4 ? 4 : k >= 2 ? 2 : 1;
-        P.groups = pick_groups(P.K * kBlock, t->L.n_dfa, P.K * kBlock);
+        // stride: the widest LDS image present, unless the plan names one
+        uint32_t S = 0;
+        for (uint32_t s : {4u, 2u, 1u})
+            if (!S && t->L.img[stride_index(s)].present) S = s;
+        uint32_t K = 2, G = 128, D = 2;
+        if (user) {
+            if (user->stride) {
+                const int si = stride_index(user->stride);
+                if (si < 0 || !t->L.img[si].present)
+                    return sfa_fail(SFA_ERR_INVALID_ARG, "plan stride not available for this table");
+                S = user->stride;
+            }
+            if (user->pieces) K = user->pieces;
+            if (user->load_bytes) G = user->load_bytes;
+            if (user->depth) D = user->depth;
+        }
+        if (S == 0) {
+            // global-table walk: K pieces of 16-byte loads
+            if (!user || !user->pieces) K = 8;
+            if (K != 1 && K != 2 && K != 4 && K != 8) return sfa_fail(SFA_ERR_INVALID_ARG, "plan pieces not supported");
+            G = 16;
+            D = 2;
+        } else if (!lds_shape_ok(K, G, D)) {
+            return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth) not supported");
+        }
+        // short chunks: fewer pieces (halving keeps a supported shape: K=1 shapes exist for G >= 64)
+        while (K > 1 && P.chunk_len < (uint64_t)K * G * 2) {
+            K /= 2;
+            if (S && !lds_shape_ok(K, G, D)) {
+                G = 64;
+                D = 2;
+            }
+        }
+        P.S = S;
+        P.K = K;
+        P.G = G;
+        P.D = D;
+        P.groups = pick_groups(P.K * kBlock, t->L.n_dfa);
     }
-    P.final_groups = pick_groups(P.blocks, t->L.n_dfa, P.blocks);
+    P.final_groups = pick_groups(P.blocks, t->L.n_dfa);
     P.ws_bytes = kWsHeader + (size_t)P.blocks * t->L.n_dfa * 4;
-    return P;
+    return SFA_OK;
 }
 
-template <int K, typename NT, typename MT, bool LDS>
-hipError_t launch_walk(const MatchArgs &a, uint32_t blocks, size_t lds, hipStream_t s) {
-    auto fn = k_sfa_walk<K, NT, MT, LDS>;
+template <typename F>
+hipError_t launch(F fn, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s, const MatchArgs &a) {
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-template <int K, typename NT, typename MT>
-hipError_t dispatch_lds(const MatchArgs &a, bool lds_tab, uint32_t blocks, size_t lds, hipStream_t s) {
-    return lds_tab ? launch_walk<K, NT, MT, true>(a, blocks, lds, s) : launch_walk<K, NT, MT, false>(a, blocks, lds, s);
+template <int S>
+hipError_t dispatch_shape(uint32_t K, uint32_t G, uint32_t D, uint32_t blocks, size_t lds, hipStream_t s,
+                          const MatchArgs &a) {
+#define SFA_SHAPE_LAUNCH(k, g, d) \
+    if (K == k && G == g && D == d) return launch(k_sfa_lds<S, k, g, d>, blocks, kBlock, lds, s, a);
+    SFA_LDS_SHAPES(SFA_SHAPE_LAUNCH)
+#undef SFA_SHAPE_LAUNCH
+    return hipErrorInvalidValue;
 }
 
-template <int K, typename NT>
-hipError_t dispatch_map(const MatchArgs &a, uint32_t map_w, bool lds_tab, uint32_t blocks, size_t lds, hipStream_t s) {
-    return map_w == 1 ? dispatch_lds<K, NT, uint8_t>(a, lds_tab, blocks, lds, s)
-                      : dispatch_lds<K, NT, uint16_t>(a, lds_tab, blocks, lds, s);
-}
-
-template <int K>
-hipError_t dispatch_next(const MatchArgs &a, const Layout &L, uint32_t blocks, size_t lds, hipStream_t s) {
-    const bool lt = L.in_lds != 0;
-    if (L.next_w == 1) return dispatch_map<K, uint8_t>(a, L.map_w, lt, blocks, lds, s);
-    if (L.next_w == 2) return dispatch_map<K, uint16_t>(a, L.map_w, lt, blocks, lds, s);
-    return dispatch_map<K, uint32_t>(a, L.map_w, lt, blocks, lds, s);
+template <typename NT>
+hipError_t dispatch_global(uint32_t K, uint32_t blocks, size_t lds, hipStream_t s, const MatchArgs &a) {
+    switch (K) {
+        case 8: return launch(k_sfa_global<8, NT>, blocks, kBlock, lds, s, a);
+        case 4: return launch(k_sfa_global<4, NT>, blocks, kBlock, lds, s, a);
+        case 2: return launch(k_sfa_global<2, NT>, blocks, kBlock, lds, s, a);
+        default: return launch(k_sfa_global<1, NT>, blocks, kBlock, lds, s, a);
+    }
 }
 
 sfa_status common_checks(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d_ws, size_t ws_bytes,
                          sfa_result *d_out, const Plan &P) {
-    if (!t) return sfa_fail(SFA_ERR_INVALID_ARG, "null table");
     if (!d_out) return sfa_fail(SFA_ERR_INVALID_ARG, "null output");
     if (n && !d_in) return sfa_fail(SFA_ERR_INVALID_ARG, "null input");
     if (!d_ws) return sfa_fail(SFA_ERR_INVALID_ARG, "null workspace");
@@ -646,82 +980,116 @@ MatchArgs base_args(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d
     a.final_groups = P.final_groups;
     a.accept = t->d_base + t->L.off_acc;
     a.map = t->d_base + t->L.off_map;
+    a.map_bytes = (uint32_t)std::min<uint64_t>(UINT32_MAX, (uint64_t)t->L.map_w * t->L.n_sfa * t->L.n_dfa);
     a.counter = (uint32_t *)d_ws;
     a.block_maps = (uint32_t *)((uint8_t *)d_ws + kWsHeader);
     a.out = d_out;
     return a;
 }
 
+size_t scratch_lds(const Plan &P, uint32_t n_dfa) {
+    return std::max<size_t>(P.groups > 1 ? (size_t)P.groups * n_dfa * 4 : 0,
+                            P.final_groups > 1 ? (size_t)P.final_groups * n_dfa * 4 : 0);
+}
+
 }  // namespace
 
 extern "C" sfa_status sfa_match_workspace_bytes(const sfa_table *t, uint64_t n, uint32_t n_chunks, size_t *out_bytes) {
     if (!t || !out_bytes) return sfa_fail(SFA_ERR_INVALID_ARG, "null argument");
-    Plan a = make_plan(t, n, n_chunks, false), b = make_plan(t, n, n_chunks, true);
+    Plan a, b;
+    sfa_status st = make_plan(t, n, n_chunks, true, nullptr, b);
+    if (st != SFA_OK) return st;
+    if (t->L.n_sfa) {
+        st = make_plan(t, n, n_chunks, false, nullptr, a);
+        if (st != SFA_OK) return st;
+    }
     *out_bytes = std::max(a.ws_bytes, b.ws_bytes);
     return SFA_OK;
 }
 
-extern "C" sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks, void *d_ws,
-                                size_t ws_bytes, sfa_result *d_out, void *stream) {
+extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
+                                   const sfa_plan *plan, void *d_ws, size_t ws_bytes, sfa_result *d_out,
+                                   void *stream) {
     if (!t) return sfa_fail(SFA_ERR_INVALID_ARG, "null table");
     if (t->L.n_sfa == 0) return sfa_fail(SFA_ERR_NO_SFA, "table has no D-SFA; use sfa_match_speculative");
-    Plan P = make_plan(t, n, n_chunks, false);
-    sfa_status st = common_checks(t, d_in, n, d_ws, ws_bytes, d_out, P);
+    Plan P;
+    sfa_status st = make_plan(t, n, n_chunks, false, plan, P);
+    if (st != SFA_OK) return st;
+    st = common_checks(t, d_in, n, d_ws, ws_bytes, d_out, P);
     if (st != SFA_OK) return st;
     MatchArgs a = base_args(t, d_in, n, d_ws, d_out, P);
-    a.row_bytes = t->L.C * t->L.next_w;
-    a.next_bytes = t->L.next_bytes;
-    a.cls = (const uint16_t *)(t->d_base + t->L.off_cls);
-    a.next = t->d_base + t->L.off_next;
-    const size_t lds = 512 + (t->L.in_lds ? ((t->L.next_bytes + 15) & ~15u) : 0) + (size_t)P.K * kBlock * 4 +
-                       std::max<size_t>(P.groups > 1 ? (size_t)P.groups * t->L.n_dfa * 4 : 0,
-                                        P.final_groups > 1 ? (size_t)P.final_groups * t->L.n_dfa * 4 : 0);
-    if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
+    hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    switch (P.K) {
-        case 8: e = dispatch_next<8>(a, t->L, P.blocks, lds, (hipStream_t)stream); break;
-        case 4: e = dispatch_next<4>(a, t->L, P.blocks, lds, (hipStream_t)stream); break;
-        case 2: e = dispatch_next<2>(a, t->L, P.blocks, lds, (hipStream_t)stream); break;
-        default: e = dispatch_next<1>(a, t->L, P.blocks, lds, (hipStream_t)stream); break;
+    if (P.S) {
+        const Image &im = t->L.img[stride_index(P.S)];
+        a.img = t->d_base + im.off;
+        a.img_bytes = im.bytes;
+        a.row_bytes = im.row_bytes;
+        a.one_off = im.one_off;
+        a.wide_mul = t->L.C * t->L.C;
+        a.region_bytes = (im.bytes + 15) & ~15u;
+        a.map_lds = a.map_bytes <= a.region_bytes;
+        a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * kBlock * 4;
+        const size_t lds = a.region_bytes + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
+        switch (P.S) {
+            case 4: e = dispatch_shape<4>(P.K, P.G, P.D, P.blocks, lds, s, a); break;
+            case 2: e = dispatch_shape<2>(P.K, P.G, P.D, P.blocks, lds, s, a); break;
+            default: e = dispatch_shape<1>(P.K, P.G, P.D, P.blocks, lds, s, a); break;
+        }
+    } else {
+        a.img = t->d_base + t->L.off_next;
+        a.cls = (const uint16_t *)(t->d_base + t->L.off_cls);
+        a.row_bytes = t->L.C * t->L.next_w;
+        a.region_bytes = 512;
+        a.map_lds = 0;
+        a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * kBlock * 4;
+        const size_t lds = 512 + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
+        if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.blocks, lds, s, a);
+        else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.blocks, lds, s, a);
+        else e = dispatch_global<uint32_t>(P.K, P.blocks, lds, s, a);
     }
     if (e != hipSuccess) return sfa_fail(SFA_ERR_HIP, std::string("walk launch: ") + hipGetErrorString(e));
     return SFA_OK;
 }
 
+extern "C" sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks, void *d_ws,
+                                size_t ws_bytes, sfa_result *d_out, void *stream) {
+    return sfa_match_ex(t, d_in, n, n_chunks, nullptr, d_ws, ws_bytes, d_out, stream);
+}
+
 extern "C" sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
                                             void *d_ws, size_t ws_bytes, sfa_result *d_out, void *stream) {
     if (!t) return sfa_fail(SFA_ERR_INVALID_ARG, "null table");
-    Plan P = make_plan(t, n, n_chunks, true);
-    sfa_status st = common_checks(t, d_in, n, d_ws, ws_bytes, d_out, P);
+    Plan P;
+    sfa_status st = make_plan(t, n, n_chunks, true, nullptr, P);
+    if (st != SFA_OK) return st;
+    st = common_checks(t, d_in, n, d_ws, ws_bytes, d_out, P);
     if (st != SFA_OK) return st;
     MatchArgs a = base_args(t, d_in, n, d_ws, d_out, P);
     a.row_bytes = t->L.C * 2;
-    a.next_bytes = 2 * t->L.n_dfa * t->L.C;
+    a.img_bytes = 2 * t->L.n_dfa * t->L.C;
     a.cls = (const uint16_t *)(t->d_base + t->L.off_dcls);
-    a.next = t->d_base + t->L.off_dnext;
+    a.img = t->d_base + t->L.off_dnext;
     const uint32_t nd = t->L.n_dfa;
-    const size_t lds = 512 + ((a.next_bytes + 15) & ~15u) +
+    a.region_bytes = 512 + ((a.img_bytes + 15) & ~15u);
+    a.map_lds = 0;
+    a.bm_lds = (uint64_t)P.blocks * nd * 2 <= a.region_bytes;
+    const size_t lds = 512 + ((a.img_bytes + 15) & ~15u) + 16 +
                        std::max<size_t>((size_t)kSpecWaves * nd * 4,
                                         P.final_groups > 1 ? (size_t)P.final_groups * nd * 4 : 0);
     if (lds > t->lds_per_block)
         return sfa_fail(SFA_ERR_INVALID_ARG, "DFA too large for the speculative kernel's LDS plan");
     const uint32_t S = (nd + 63) / 64;
-    hipError_t e;
-    const dim3 grid(P.blocks), block(kSpecWaves * 64);
     hipStream_t s = (hipStream_t)stream;
-    auto go = [&](auto fn) -> hipError_t {
-        if (lds > 64 * 1024) {
-            hipError_t e2 = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e2 != hipSuccess) return e2;
-        }
-        hipLaunchKernelGGL(fn, grid, block, lds, s, a);
-        return hipGetLastError();
-    };
-    if (S <= 1) e = go(k_spec_walk<1>);
-    else if (S <= 2) e = go(k_spec_walk<2>);
-    else if (S <= 4) e = go(k_spec_walk<4>);
-    else if (S <= 8) e = go(k_spec_walk<8>);
-    else if (S <= 16) e = go(k_spec_walk<16>);
+    const uint32_t threads = kSpecWaves * 64;
+    hipError_t e;
+    if (S <= 1) e = launch(k_spec_walk<1>, P.blocks, threads, lds, s, a);
+    else if (S <= 2) e = launch(k_spec_walk<2>, P.blocks, threads, lds, s, a);
+    else if (S <= 4) e = launch(k_spec_walk<4>, P.blocks, threads, lds, s, a);
+    else if (S <= 8) e = launch(k_spec_walk<8>, P.blocks, threads, lds, s, a);
+    else if (S <= 16) e = launch(k_spec_walk<16>, P.blocks, threads, lds, s, a);
     else return sfa_fail(SFA_ERR_INVALID_ARG, "speculative kernel supports at most 1024 DFA states");
     if (e != hipSuccess) return sfa_fail(SFA_ERR_HIP, std::string("speculative launch: ") + hipGetErrorString(e));
     return SFA_OK;

@@ -47,7 +47,10 @@ class Compiled:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().sfa_compiled_free(h)
+            try:
+                lib().sfa_compiled_free(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def desc(self) -> _capi.TableDesc:
@@ -109,7 +112,10 @@ class Table:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().sfa_free_table(h)
+            try:
+                lib().sfa_free_table(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     @property
@@ -137,7 +143,8 @@ def load(compiled: Compiled, **kw) -> Table:
     return Table(compiled, **kw)
 
 
-def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: torch.Tensor | None, stream):
+def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: torch.Tensor | None, stream,
+           plan: dict | None = None):
     if data.dtype != torch.uint8 or not data.is_cuda or data.dim() != 1 or not data.is_contiguous():
         raise ValueError("data must be a contiguous 1-D torch.uint8 tensor on a HIP device")
     if data.device != table.device:
@@ -146,16 +153,24 @@ def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: t
     ws = table.workspace(n, n_chunks, stream)
     if out is None:
         out = torch.empty(2, dtype=torch.int32, device=table.device)
-    check(getattr(lib(), fn_name)(table.handle, ctypes.c_void_p(data.data_ptr() if n else 0), n, n_chunks,
-                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
-                                  ctypes.c_void_p(_stream_ptr(stream))))
+    args = [table.handle, ctypes.c_void_p(data.data_ptr() if n else 0), n, n_chunks]
+    if plan is not None:
+        fn_name = "sfa_match_ex"
+        args.append(ctypes.byref(_capi.Plan(int(plan.get("stride", 0)), int(plan.get("pieces", 0)),
+                                             int(plan.get("load_bytes", 0)), int(plan.get("depth", 0)))))
+    args += [ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
+             ctypes.c_void_p(_stream_ptr(stream))]
+    check(getattr(lib(), fn_name)(*args))
     return out
 
 
 def match(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor | None = None,
-          stream=None) -> torch.Tensor:
-    """Algorithm 5 on the device; returns int32[2] = (final state, accept) on the device."""
-    return _match("sfa_match", table, data, n_chunks, out, stream)
+          stream=None, plan: dict | None = None) -> torch.Tensor:
+    """Algorithm 5 on the device; returns int32[2] = (final state, accept) on the device.
+
+    ``plan`` (optional) is {"stride", "pieces", "load_bytes", "depth"} as in sfa_plan.
+    """
+    return _match("sfa_match", table, data, n_chunks, out, stream, plan)
 
 
 def match_speculative(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor | None = None,

@@ -208,15 +208,21 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  *   load_bytes  G: bytes of one piece loaded per step (16, 32, 64, 128).
  *   depth       D: load steps in flight per piece (loads for step j + D - 1
  *               are issued before step j is walked).
- * Supported (K, G, D): (1,64,2) (1,64,4) (1,128,2) (1,128,3) (1,128,4)
- * (2,32,4) (2,64,2) (2,64,3) (2,64,4) (2,128,2) (4,32,2) (4,32,4) (4,64,2)
- * (8,16,2) (8,32,2); tables in global memory use K in {1,2,4,8} only.
- * Other values give SFA_ERR_INVALID_ARG. */
+ *   block_threads    TB: threads per block (256, 512, 1024).
+ *   lanes_per_chunk  consecutive lanes that share a chunk (power of two
+ *               <= 16); the chunk is cut into lanes_per_chunk * K pieces.
+ * Supported (K, G, D, TB): TB=256: (1,64,2) (1,128,2) (1,128,4) (2,64,2)
+ * (2,64,4) (2,128,2) (4,64,2) (8,32,2); TB=512: (1,64,2) (1,128,2) (2,64,2)
+ * (2,128,2) (4,32,2) (4,64,2); TB=1024: (1,32,2) (1,64,2) (1,128,2) (2,32,2)
+ * (2,64,2).  Tables in global memory use TB=256, lanes_per_chunk=1 and
+ * K in {1,2,4,8}.  Other values give SFA_ERR_INVALID_ARG. */
 typedef struct sfa_plan {
     uint32_t stride;
     uint32_t pieces;
     uint32_t load_bytes;
     uint32_t depth;
+    uint32_t block_threads;
+    uint32_t lanes_per_chunk;
 } sfa_plan;
 
 sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
@@ -230,6 +236,59 @@ sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint64_t n, uin
 sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64_t n,
                                  uint32_t n_chunks, void *d_ws, size_t ws_bytes,
                                  sfa_result *d_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched matching: many (document, table) jobs in one launch sequence.
+ *
+ *   Documents are byte ranges of one device buffer, doc d = [doc_off[d],
+ *   doc_off[d+1]).  A job (doc, table) is matched exactly as sfa_match would
+ *   (whole-document membership, Algorithm 5 with the document cut into pieces
+ *   of piece_bytes; any division is valid, Theorem 2); its result goes to
+ *   d_out[job index].  Every table must have a D-SFA whose stride-1 walk table
+ *   is at most 64 KiB (sfa_table_info.strides bit 1).
+ *
+ *   sfa_batch_create   host planning (pieces, units, groups); doc_off and jobs
+ *                      are host arrays, copied into the plan.  tables must stay
+ *                      loaded while the plan is used.
+ *   sfa_batch_workspace_bytes / sfa_batch_upload
+ *                      the caller provides a device workspace (256-byte
+ *                      aligned) and uploads the plan's descriptors into it once
+ *                      (async on stream).
+ *   sfa_match_batch    launches the walk, group and composition kernels only
+ *                      (no allocation, no host synchronisation, no memset),
+ *                      so a stream capture of it can be replayed as a graph as
+ *                      long as the workspace and table buffers stay in place.
+ *                      The document bytes may change between calls.
+ *   sfa_batch_free     frees the host plan.
+ * ---------------------------------------------------------------------- */
+typedef struct sfa_batch sfa_batch;
+
+typedef struct sfa_batch_options {
+    uint32_t piece_bytes;     /* bytes per piece, multiple of 16 (0 = 4096) */
+    uint32_t group_pieces;    /* pieces per group for jobs longer than that (0 = 32) */
+    uint32_t units_per_lane;  /* pieces walked together by one lane: 1, 2 or 4 (0 = 2) */
+    uint32_t force_global;    /* 1: read walk tables from global memory instead of LDS */
+} sfa_batch_options;
+
+typedef struct sfa_batch_info {
+    uint32_t n_jobs;
+    uint32_t n_docs;          /* documents referenced by at least one job */
+    uint64_t n_units;         /* (piece, job) work units */
+    uint64_t n_group_items;   /* (job, group, start state) items of long jobs */
+    uint32_t piece_bytes, group_pieces, units_per_lane, tables_in_lds;
+    uint64_t workspace_bytes;
+} sfa_batch_info;
+
+sfa_status sfa_batch_create(const sfa_table *const *tables, uint32_t n_tables,
+                            const uint64_t *doc_off /* host [n_docs + 1] */, uint32_t n_docs,
+                            const uint32_t *jobs /* host [2 * n_jobs]: doc, table */, uint32_t n_jobs,
+                            const sfa_batch_options *opts, sfa_batch **out);
+sfa_status sfa_batch_get_info(const sfa_batch *b, sfa_batch_info *out);
+sfa_status sfa_batch_workspace_bytes(const sfa_batch *b, size_t *out_bytes);
+sfa_status sfa_batch_upload(const sfa_batch *b, void *d_ws, size_t ws_bytes, void *stream);
+sfa_status sfa_match_batch(const sfa_batch *b, const uint8_t *d_data, void *d_ws, size_t ws_bytes,
+                           sfa_result *d_out /* [n_jobs] */, void *stream);
+void       sfa_batch_free(sfa_batch *b);
 
 #ifdef __cplusplus
 }

@@ -10,3 +10,4 @@ The matcher is libsfa.so (C ABI in include/sfa.h); this package binds it.
 """
 from ._capi import SfaError, ParseError, lib  # noqa: F401
 from .matcher import Compiled, Table, compile, load, match, match_speculative  # noqa: F401
+from .batch import Autotuner, Batch, BatchOptions, GraphBatch, match_batch  # noqa: F401

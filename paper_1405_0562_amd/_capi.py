@@ -61,7 +61,19 @@ class TableInfo(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("stride", ctypes.c_uint32), ("pieces", ctypes.c_uint32), ("load_bytes", ctypes.c_uint32),
-                ("depth", ctypes.c_uint32)]
+                ("depth", ctypes.c_uint32), ("block_threads", ctypes.c_uint32), ("lanes_per_chunk", ctypes.c_uint32)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("piece_bytes", ctypes.c_uint32), ("group_pieces", ctypes.c_uint32),
+                ("units_per_lane", ctypes.c_uint32), ("force_global", ctypes.c_uint32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_jobs", ctypes.c_uint32), ("n_docs", ctypes.c_uint32), ("n_units", ctypes.c_uint64),
+                ("n_group_items", ctypes.c_uint64), ("piece_bytes", ctypes.c_uint32),
+                ("group_pieces", ctypes.c_uint32), ("units_per_lane", ctypes.c_uint32),
+                ("tables_in_lds", ctypes.c_uint32), ("workspace_bytes", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -88,6 +100,13 @@ SIGNATURES = {
     "sfa_match": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _SZ, _P, _P]),
     "sfa_match_speculative": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _SZ, _P, _P]),
     "sfa_match_ex": (ctypes.c_int, [_P, _P, _U64, _U32, ctypes.POINTER(Plan), _P, _SZ, _P, _P]),
+    "sfa_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), _U32, _P, _U32, _P, _U32,
+                                        ctypes.POINTER(BatchOptions), ctypes.POINTER(_P)]),
+    "sfa_batch_get_info": (ctypes.c_int, [_P, ctypes.POINTER(BatchInfo)]),
+    "sfa_batch_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_SZ)]),
+    "sfa_batch_upload": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "sfa_match_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _P, _P]),
+    "sfa_batch_free": (None, [_P]),
 }
 
 _lib = None

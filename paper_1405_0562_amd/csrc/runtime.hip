@@ -59,56 +59,14 @@ constexpr uint32_t kBlock = 256;             // threads per block of the walk ke
 constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
 constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
 constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
-constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K <= 8)
+constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K * block threads <= 2048)
 constexpr uint32_t kPairTable = 65536;       // byte-pair class table entries (u8)
 constexpr uint64_t kWsHeader = 256;          // control word area at the start of a workspace
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-// A stride-S walk image, copied as one block into LDS by the walk kernel:
-//   [pair-class table u8[65536] (S >= 2)] [byte-class table u8[256]]
-//   [rows: n_sfa x (C^S (+ C if S >= 2)) u16 entries]
-// Class and pair-class entries hold column offsets in bytes (2 * index).
-// Entry values are row offsets in bytes (state id * row bytes), so one
-// transition is a single LDS load at (current row offset + column * 2).
-// Columns 0..C^S-1 hold delta_s applied to an S-byte word whose class digits
-// c_0..c_{S-1} (first byte most significant, base C) form the column index;
-// for S >= 2 the last C columns hold the single-byte transition (used for
-// unaligned heads and short tails).
-struct Image {
-    uint32_t present = 0;
-    uint32_t bytes = 0;       // total image bytes
-    uint32_t row_bytes = 0;   // RS
-    uint32_t one_off = 0;     // byte offset of the single-byte columns in a row
-    uint64_t off = 0;         // offset in the device buffer
-};
-
-struct Layout {
-    uint32_t n_dfa = 0, n_sfa = 0, C = 0, q0 = 0;
-    uint32_t next_w = 0, map_w = 0;
-    uint64_t off_cls = 0;    // u16[256]: cls[b] * next_w   (global-table walk)
-    uint64_t off_dcls = 0;   // u16[256]: cls[b] * 2        (speculative kernel)
-    uint64_t off_acc = 0;    // u8[n_dfa]
-    uint64_t off_dnext = 0;  // u16[n_dfa * C]
-    uint64_t off_next = 0;   // next_w bytes [n_sfa * C]: state ids (global-table walk)
-    uint64_t off_map = 0;    // map_w bytes [n_sfa * n_dfa]
-    Image img[3];            // strides 1, 2, 4
-    uint64_t total = 0;
-    uint64_t next_bytes = 0;
-};
-
-inline int stride_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : -1; }
-
 }  // namespace
 
-struct sfa_table {
-    Layout L;
-    uint8_t *d_base = nullptr;
-    int device = 0;
-    uint32_t lds_per_block = 0;
-    uint32_t num_cus = 0;
-    std::vector<uint8_t> image;
-};
 
 namespace {
 
@@ -360,6 +318,7 @@ struct MatchArgs {
     uint32_t map_lds;        // 1: the mapping rows are copied into that region for the block composition
     uint32_t map_bytes;      // bytes of the mapping rows
     uint32_t bm_lds;         // 1: the last block stages all block mappings (u16) in LDS
+    uint32_t lanes_per_chunk;  // LPC: consecutive lanes sharing one chunk (walk kernels)
     const uint16_t *cls;     // global walk / speculative: u16[256] class column offsets
     const uint8_t *img;      // LDS image, global walk table, or u16 DFA table
     const uint8_t *map;      // mapping rows
@@ -501,12 +460,17 @@ __device__ __forceinline__ uint32_t word_of(const uint4 &v, int d) {
     return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
 }
 
-// Chunk bounds of this lane and the split of the chunk into K pieces whose
-// lengths are multiples of Q (so every piece starts at the same alignment).
-template <int K, int Q>
+// Chunk bounds of this lane and its K pieces.  LPC consecutive lanes share a
+// chunk: the chunk is cut into LPC * K pieces whose lengths are multiples of
+// Q (so every piece starts at the same alignment) and lane part j of the
+// chunk walks pieces j*K .. j*K + K - 1, i.e. piece order is text order.
+template <int K, int Q, int TB>
 __device__ __forceinline__ void lane_pieces(const MatchArgs &a, uint64_t &c0, uint64_t &c1, uint64_t *pos,
                                             uint64_t *end) {
-    const uint64_t chunk = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t lane = (uint64_t)blockIdx.x * TB + threadIdx.x;
+    const uint32_t lpc = a.lanes_per_chunk;
+    const uint64_t chunk = lane / lpc;
+    const uint32_t part = (uint32_t)(lane - chunk * lpc);
     c0 = a.n;
     c1 = a.n;
     if (chunk < a.n_chunks) {
@@ -514,10 +478,11 @@ __device__ __forceinline__ void lane_pieces(const MatchArgs &a, uint64_t &c0, ui
         c1 = min(a.n, c0 + a.chunk_len);
     }
     const uint64_t len = c1 - c0;
-    const uint64_t piece = (((len + K - 1) / K) + Q - 1) / Q * Q;
+    const uint64_t np = (uint64_t)lpc * K;
+    const uint64_t piece = (((len + np - 1) / np) + Q - 1) / Q * Q;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        pos[k] = min(c1, c0 + k * piece);
+        pos[k] = min(c1, c0 + ((uint64_t)part * K + k) * piece);
         end[k] = min(c1, pos[k] + piece);
     }
 }
@@ -526,19 +491,19 @@ __device__ __forceinline__ void lane_pieces(const MatchArgs &a, uint64_t &c0, ui
 // G bytes of each piece loaded per step, loads issued D - 1 steps ahead.  Lane l of block b owns chunk
 // c = b*256 + l; its K piece states (in text order) join the block
 // composition, then the grid composition.
-template <int S, int K, int G, int D>
-__global__ __launch_bounds__(kBlock) void k_sfa_lds(MatchArgs a) {
+template <int S, int K, int G, int D, int TB>
+__global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr uint32_t CLS = (S >= 2) ? kPairTable : 0u;   // byte-class table
     constexpr uint32_t TAB = CLS + 256;                     // rows
     const uint32_t img = (a.img_bytes + 15) & ~15u;
     uint32_t *s_ids = (uint32_t *)(smem + img);
-    uint32_t *s_flag = s_ids + K * kBlock;
+    uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
     {
         const uint4 *src = (const uint4 *)a.img;
         uint4 *dst = (uint4 *)smem;
-        for (uint32_t i = threadIdx.x; i < img / 16; i += kBlock) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < img / 16; i += TB) dst[i] = src[i];
     }
     __syncthreads();
 
@@ -548,14 +513,14 @@ __global__ __launch_bounds__(kBlock) void k_sfa_lds(MatchArgs a) {
     auto step1 = [&](uint32_t st, uint32_t b) -> uint32_t { return row(st + one + smem[CLS + b]); };
 
     uint64_t c0, c1, pos[K], end[K];
-    lane_pieces<K, G>(a, c0, c1, pos, end);
+    lane_pieces<K, G, TB>(a, c0, c1, pos, end);
     uint32_t st[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = 0;     // f_I
 
     if (c1 > c0) {
         // head: single bytes up to 16-byte alignment (the same for all pieces)
-        const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + c0) & 15)) & 15);
+        const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15);
         for (uint32_t i = 0; i < head; ++i) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -673,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_sfa_lds(MatchArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k] / rs;
     __syncthreads();   // the walk is over: the image region may be reused
-    const uint32_t E = K * kBlock;
+    const uint32_t E = K * TB;
     uint32_t *bmap = a.block_maps + (size_t)blockIdx.x * a.n_dfa;
     if (a.n_dfa <= 256)
         compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
@@ -699,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
         return *(const NT *)(tab + (size_t)__umul24(s, rb) + s_cls[b]);
     };
     uint64_t c0, c1, pos[K], end[K];
-    lane_pieces<K, 16>(a, c0, c1, pos, end);
+    lane_pieces<K, 16, kBlock>(a, c0, c1, pos, end);
     uint32_t st[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = 0;
@@ -837,21 +802,23 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
 // ---------------------------------------------------------------------------
 // host-side launch
 // ---------------------------------------------------------------------------
-// Supported (pieces K, load bytes G, prefetch depth D) shapes of the LDS walk.
+// Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
+// shapes of the LDS walk.  K * G * D bounds the load buffers in registers.
 #define SFA_LDS_SHAPES(X) \
-    X(1, 64, 2) X(1, 64, 4) X(1, 128, 2) X(1, 128, 3) X(1, 128, 4) \
-    X(2, 32, 4) X(2, 64, 2) X(2, 64, 3) X(2, 64, 4) X(2, 128, 2) \
-    X(4, 32, 2) X(4, 32, 4) X(4, 64, 2) X(8, 16, 2) X(8, 32, 2)
+    X(1, 64, 2, 256) X(1, 128, 2, 256) X(1, 128, 4, 256) X(2, 64, 2, 256) X(2, 64, 4, 256) \
+    X(2, 128, 2, 256) X(4, 64, 2, 256) X(8, 32, 2, 256) \
+    X(1, 64, 2, 512) X(1, 128, 2, 512) X(2, 64, 2, 512) X(2, 128, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
+    X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
 
-bool lds_shape_ok(uint32_t K, uint32_t G, uint32_t D) {
-#define SFA_SHAPE_OK(k, g, d) if (K == k && G == g && D == d) return true;
+bool lds_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
+#define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
     SFA_LDS_SHAPES(SFA_SHAPE_OK)
 #undef SFA_SHAPE_OK
     return false;
 }
 
 struct Plan {
-    uint32_t n_chunks = 0, blocks = 0, S = 0, K = 1, G = 16, D = 2, groups = 1, final_groups = 1;
+    uint32_t n_chunks = 0, blocks = 0, S = 0, K = 1, G = 16, D = 2, TB = kBlock, LPC = 1, groups = 1, final_groups = 1;
     uint64_t chunk_len = 0;
     size_t ws_bytes = 0;
 };
@@ -869,23 +836,23 @@ uint32_t pick_groups(uint32_t E, uint32_t n_dfa) {
 
 sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool speculative, const sfa_plan *user,
                      Plan &P) {
-    const uint32_t per_block = speculative ? kSpecWaves : kBlock;
     if (n_chunks == 0) {
         const uint64_t target = speculative ? 4096 : 1024;   // bytes per chunk at least
-        const uint64_t max_chunks = (uint64_t)std::max(1u, t->num_cus) * per_block * (speculative ? 8 : 1);
+        const uint64_t max_chunks = (uint64_t)std::max(1u, t->num_cus) * (speculative ? kSpecWaves * 8 : kBlock);
         uint64_t p = std::max<uint64_t>(1, (n + target - 1) / target);
         P.n_chunks = (uint32_t)std::min(p, max_chunks);
     } else {
         P.n_chunks = n_chunks;
     }
     P.chunk_len = n ? (n + P.n_chunks - 1) / P.n_chunks : 0;
-    P.blocks = (uint32_t)((P.n_chunks + per_block - 1) / per_block);
-    if (!speculative) {
+    if (speculative) {
+        P.blocks = (uint32_t)((P.n_chunks + kSpecWaves - 1) / kSpecWaves);
+    } else {
         // stride: the widest LDS image present, unless the plan names one
         uint32_t S = 0;
         for (uint32_t s : {4u, 2u, 1u})
             if (!S && t->L.img[stride_index(s)].present) S = s;
-        uint32_t K = 2, G = 128, D = 2;
+        uint32_t K = 2, G = 128, D = 2, TB = 256, LPC = 1;
         if (user) {
             if (user->stride) {
                 const int si = stride_index(user->stride);
@@ -896,29 +863,41 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
             if (user->pieces) K = user->pieces;
             if (user->load_bytes) G = user->load_bytes;
             if (user->depth) D = user->depth;
+            if (user->block_threads) TB = user->block_threads;
+            if (user->lanes_per_chunk) LPC = user->lanes_per_chunk;
         }
+        if (LPC == 0 || (LPC & (LPC - 1)) || LPC > 16)
+            return sfa_fail(SFA_ERR_INVALID_ARG, "plan lanes_per_chunk must be a power of two <= 16");
         if (S == 0) {
-            // global-table walk: K pieces of 16-byte loads
+            // global-table walk: 256-thread blocks, K pieces of 16-byte loads
             if (!user || !user->pieces) K = 8;
             if (K != 1 && K != 2 && K != 4 && K != 8) return sfa_fail(SFA_ERR_INVALID_ARG, "plan pieces not supported");
             G = 16;
             D = 2;
-        } else if (!lds_shape_ok(K, G, D)) {
-            return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth) not supported");
+            TB = kBlock;
+            LPC = 1;
+        } else if (!lds_shape_ok(K, G, D, TB)) {
+            return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth, block_threads) not supported");
         }
-        // short chunks: fewer pieces (halving keeps a supported shape: K=1 shapes exist for G >= 64)
-        while (K > 1 && P.chunk_len < (uint64_t)K * G * 2) {
+        if (LPC > TB) return sfa_fail(SFA_ERR_INVALID_ARG, "plan lanes_per_chunk exceeds block_threads");
+        // short chunks: fewer pieces, then fewer lanes per chunk
+        while (K > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) {
             K /= 2;
-            if (S && !lds_shape_ok(K, G, D)) {
+            if (S && !lds_shape_ok(K, G, D, TB)) {
                 G = 64;
                 D = 2;
             }
         }
+        while (LPC > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) LPC /= 2;
+        if (S && !lds_shape_ok(K, G, D, TB)) return sfa_fail(SFA_ERR_INVALID_ARG, "no launch shape for this plan");
         P.S = S;
         P.K = K;
         P.G = G;
         P.D = D;
-        P.groups = pick_groups(P.K * kBlock, t->L.n_dfa);
+        P.TB = TB;
+        P.LPC = LPC;
+        P.blocks = (uint32_t)(((uint64_t)P.n_chunks * LPC + TB - 1) / TB);
+        P.groups = pick_groups(P.K * TB, t->L.n_dfa);
     }
     P.final_groups = pick_groups(P.blocks, t->L.n_dfa);
     P.ws_bytes = kWsHeader + (size_t)P.blocks * t->L.n_dfa * 4;
@@ -936,10 +915,10 @@ hipError_t launch(F fn, uint32_t blocks, uint32_t threads, size_t lds, hipStream
 }
 
 template <int S>
-hipError_t dispatch_shape(uint32_t K, uint32_t G, uint32_t D, uint32_t blocks, size_t lds, hipStream_t s,
+hipError_t dispatch_shape(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds, hipStream_t s,
                           const MatchArgs &a) {
-#define SFA_SHAPE_LAUNCH(k, g, d) \
-    if (K == k && G == g && D == d) return launch(k_sfa_lds<S, k, g, d>, blocks, kBlock, lds, s, a);
+#define SFA_SHAPE_LAUNCH(k, g, d, tb) \
+    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_lds<S, k, g, d, tb>, blocks, tb, lds, s, a);
     SFA_LDS_SHAPES(SFA_SHAPE_LAUNCH)
 #undef SFA_SHAPE_LAUNCH
     return hipErrorInvalidValue;
@@ -978,6 +957,7 @@ MatchArgs base_args(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d
     a.q0 = t->L.q0;
     a.groups = P.groups;
     a.final_groups = P.final_groups;
+    a.lanes_per_chunk = P.LPC;
     a.accept = t->d_base + t->L.off_acc;
     a.map = t->d_base + t->L.off_map;
     a.map_bytes = (uint32_t)std::min<uint64_t>(UINT32_MAX, (uint64_t)t->L.map_w * t->L.n_sfa * t->L.n_dfa);
@@ -1029,13 +1009,13 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.wide_mul = t->L.C * t->L.C;
         a.region_bytes = (im.bytes + 15) & ~15u;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * kBlock * 4;
-        const size_t lds = a.region_bytes + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * P.TB * 4;
+        const size_t lds = a.region_bytes + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         switch (P.S) {
-            case 4: e = dispatch_shape<4>(P.K, P.G, P.D, P.blocks, lds, s, a); break;
-            case 2: e = dispatch_shape<2>(P.K, P.G, P.D, P.blocks, lds, s, a); break;
-            default: e = dispatch_shape<1>(P.K, P.G, P.D, P.blocks, lds, s, a); break;
+            case 4: e = dispatch_shape<4>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a); break;
+            case 2: e = dispatch_shape<2>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a); break;
+            default: e = dispatch_shape<1>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a); break;
         }
     } else {
         a.img = t->d_base + t->L.off_next;

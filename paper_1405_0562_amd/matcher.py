@@ -156,8 +156,7 @@ def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: t
     args = [table.handle, ctypes.c_void_p(data.data_ptr() if n else 0), n, n_chunks]
     if plan is not None:
         fn_name = "sfa_match_ex"
-        args.append(ctypes.byref(_capi.Plan(int(plan.get("stride", 0)), int(plan.get("pieces", 0)),
-                                             int(plan.get("load_bytes", 0)), int(plan.get("depth", 0)))))
+        args.append(ctypes.byref(_capi.Plan(*(int(plan.get(f, 0)) for f, _ in _capi.Plan._fields_))))
     args += [ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
              ctypes.c_void_p(_stream_ptr(stream))]
     check(getattr(lib(), fn_name)(*args))
@@ -168,7 +167,8 @@ def match(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor
           stream=None, plan: dict | None = None) -> torch.Tensor:
     """Algorithm 5 on the device; returns int32[2] = (final state, accept) on the device.
 
-    ``plan`` (optional) is {"stride", "pieces", "load_bytes", "depth"} as in sfa_plan.
+    ``plan`` (optional) is a dict with any of the sfa_plan fields ("stride", "pieces",
+    "load_bytes", "depth", "block_threads", "lanes_per_chunk").
     """
     return _match("sfa_match", table, data, n_chunks, out, stream, plan)
 

@@ -69,6 +69,142 @@ def cpu_baseline(rx, data, budget_s: float):
     }, [full_q, int(d.accept[full_q])]
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    with open(os.path.join(ROOT, "paper_1405_0562_amd", "csrc", "runtime.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed PMC record, or None if the
+    record is missing or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or not kernel.startswith(rec.get("kernel", "?")):
+        return None
+    return rec.get("traffic_bytes")
+
+
+def batching_leg(seed: int, n_docs: int, plain_docs: int):
+    """Batched form on the batching workload vs the plain per-job path."""
+    import numpy as np
+    import torch
+    import paper_1405_0562_amd as sfa
+    import workloads as W
+    from oracle.automata import compile_regex
+    from oracle import scan
+
+    regexes = W.c4_regexes(seed)
+    tables = [sfa.load(sfa.compile(rx)) for rx in regexes]
+    data, off = W.c4_docs(seed, n_docs)
+    x = torch.from_numpy(data).cuda()
+    nt = len(tables)
+    jobs = np.array([(d, t) for d in range(n_docs) for t in range(nt)], dtype=np.uint32)
+    tuner = sfa.Autotuner(cache_path=os.path.join("/tmp", "sfa_autotune_bench.json"), reps=2)
+    opt, entry = tuner.tune(tables, x, off, jobs)
+    b = sfa.Batch(tables, off, jobs, opt)
+    g = sfa.GraphBatch(b, x)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 5
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(reps):
+        g.replay()
+    e_ev.record()
+    torch.cuda.synchronize()
+    batch_ms = s_ev.elapsed_time(e_ev) / reps
+    got = b.out.cpu().numpy()
+    # parity on a sample of documents
+    ok = True
+    dfas = [compile_regex(rx) for rx in regexes]
+    for d in range(0, n_docs, max(1, n_docs // 64)):
+        for t in range(nt):
+            q = scan.scan(dfas[t], data[off[d]:off[d + 1]])
+            ok = ok and got[d * nt + t].tolist() == [q, int(dfas[t].accept[q])]
+    # plain path: one sfa_match per job, in job order, on one stream
+    outs = torch.empty((plain_docs * nt, 2), dtype=torch.int32, device="cuda")
+    views = [x[off[d]:off[d + 1]] for d in range(plain_docs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in range(plain_docs):
+        for t in range(nt):
+            sfa.match(tables[t], views[d], out=outs[d * nt + t])
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    ok = ok and np.array_equal(outs.cpu().numpy(), got[:plain_docs * nt])
+    total = int(off[-1])
+    return {
+        "workload": "%d docs (lognormal, median 4 KiB, sigma 2, max %d B) x %d regexes, %d jobs, %.1f MB"
+                    % (n_docs, int(np.diff(off).max()), nt, len(jobs), total / 1e6),
+        "batch_ms": batch_ms, "docs_per_s": n_docs / (batch_ms * 1e-3), "jobs_per_s": len(jobs) / (batch_ms * 1e-3),
+        "matched_gbs": total * nt / (batch_ms * 1e-3) / 1e9, "unique_input_gbs": total / (batch_ms * 1e-3) / 1e9,
+        "plain_docs_per_s": plain_docs / plain_s, "plain_jobs_per_s": plain_docs * nt / plain_s,
+        "plain_sample_docs": plain_docs, "speedup_docs_per_s": (n_docs / (batch_ms * 1e-3)) / (plain_docs / plain_s),
+        "options": {"piece_bytes": opt.piece_bytes, "units_per_lane": opt.units_per_lane},
+        "graph_replayed": True, "parity_sampled": ok,
+    }
+
+
+def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0)):
+    """Continuous-batching server vs the plain FIFO path under the same
+    Poisson arrivals, at several multiples of the plain path's saturation rate."""
+    import numpy as np
+    import paper_1405_0562_amd as sfa
+    import workloads as W
+    from paper_1405_0562_amd.serve import GpuBackend, PlainBackend, Server, run_open_loop, Request
+
+    regexes = W.c5_regexes(seed)
+    tables = [sfa.load(sfa.compile(rx)) for rx in regexes]
+    plain = PlainBackend(tables)
+    # plain saturation rate R, closed loop
+    probe = W.c5_requests(seed + 100, n_req=300, qps=1.0)
+    for r in probe[:20]:
+        plain.run_one(Request(0, r.table, r.data, 0.0))
+    t0 = time.perf_counter()
+    for r in probe:
+        plain.run_one(Request(0, r.table, r.data, 0.0))
+    R = len(probe) / (time.perf_counter() - t0)
+    backend = GpuBackend(tables, pool_bytes=1 << 30, n_streams=3)
+    points = []
+    for mult in loads:
+        qps = mult * R
+        reqs = W.c5_requests(seed, n_req=n_req, qps=qps)
+        arrivals = [(r.arrival_s, r.table, r.data) for r in reqs]
+        srv = Server(backend, pool_bytes=1 << 30, max_inflight=3, big_bytes=8 << 20)
+        run_open_loop(srv, arrivals)
+        st = srv.latency_stats()
+        served = {r.rid: r.result for r in srv.finished}
+        # plain FIFO under the same arrivals: one request at a time, in order
+        t0 = time.perf_counter()
+        lat, equal = [], True
+        for i, (at, tb, data) in enumerate(arrivals):
+            now = time.perf_counter() - t0
+            if now < at:
+                time.sleep(at - now)
+            res = plain.run_one(Request(i, tb, data, at))
+            lat.append(time.perf_counter() - t0 - at)
+            equal = equal and served.get(i) == res
+        span = time.perf_counter() - t0
+        lat = np.array(lat)
+        total = sum(int(a[2].size) for a in arrivals)
+        points.append({"load_x_plain_saturation": mult, "qps": qps,
+                       "served": {k: st[k] for k in ("p50_ms", "p99_ms", "gbs", "launches")},
+                       "plain_fifo": {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                      "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                                      "gbs": total / max(1e-9, span) / 1e9},
+                       "results_equal_plain": equal})
+    return {"workload": "%d requests per load point, Pareto(1.2, 1 KiB) lengths up to 64 MiB, 16 tables, "
+                        "Poisson arrivals; plain saturation %.0f req/s" % (n_req, R),
+            "plain_saturation_qps": R, "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +216,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--speculative-steps", type=int, default=3)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-docs", type=int, default=10000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of the workload size (counter calibration)")
     args = ap.parse_args()
@@ -153,6 +293,11 @@ def main():
     cpu, want = (None, None)
     if not args.no_cpu:
         cpu, want = cpu_baseline(rx, host, args.cpu_budget)
+    kname = "k_sfa_lds" if use_sfa and table.info["table_in_lds"] else ("k_sfa_global" if use_sfa else "k_spec_walk")
+    del bufs
+    torch.cuda.empty_cache()
+    batching = None if args.no_batch else batching_leg(args.seed, args.batch_docs, min(250, args.batch_docs))
+    serving = None if args.no_serve else serving_leg(args.seed, args.serve_requests)
 
     line = {
         "metric": METRIC,
@@ -173,14 +318,16 @@ def main():
                    "n_dfa": comp.info.n_dfa, "n_sfa": comp.info.n_sfa, "n_classes": comp.info.n_classes,
                    "table_in_lds": table.info["table_in_lds"], "path": "sfa" if use_sfa else "speculative"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sfa_walk" if use_sfa else "k_spec_walk", "kernel_avg_ms": kern_avg_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload, kname),
+                     "kernel": kname, "kernel_avg_ms": kern_avg_ms,
                      "algorithmic_bytes_per_launch": n},
         "cpu_baseline": cpu,
         "result": got,
         "oracle_result": want,
         "parity": (got == want) if want is not None else None,
         "speculative": spec,
+        "batching": batching,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     if want is not None and got != want:

@@ -145,17 +145,26 @@ sfa_status sfa_compiled_desc(const sfa_compiled *c, sfa_table_desc *out);
  *     handle, so desc's arrays may be freed on return.  d_buf must stay
  *     allocated, and unmodified, while the handle is used.
  *   opts may be NULL (defaults).  force_global = 1 keeps the walk table in
- *   global memory even when it would fit LDS.
+ *   global memory even when it would fit LDS.  A D-SFA whose walk table does
+ *   not fit is walked with its most visited rows staged in LDS (as many as
+ *   lds_budget holds) and the rest read from global memory; to choose those
+ *   rows the loader renumbers the D-SFA states by visit count in a profiling
+ *   walk over profile_sample (host bytes like the input) or, without a
+ *   sample, over uniformly random byte classes.  Renumbering changes only
+ *   internal ids: results are DFA states and never depend on it.
  *   sfa_free_table frees the host handle only; the caller frees d_buf after
  *   work that uses it has finished.
  * ---------------------------------------------------------------------- */
 typedef struct sfa_table sfa_table;
 
 typedef struct sfa_load_options {
-    uint32_t force_global;   /* 0: LDS when it fits; 1: always global */
-    uint32_t lds_budget;     /* bytes of LDS the walk table may take; 0 = default (96 KiB) */
-    uint32_t no_monoid;      /* 1: never build the D-SFA product table */
+    uint32_t force_global;   /* 0: LDS when it fits; 1: walk tables read from global memory */
+    uint32_t lds_budget;     /* bytes of LDS the walk table (or its hot rows) may take; 0 = default */
+    uint32_t renumber;       /* 0: renumber states by visit count when the table is walked from
+                                global memory; 1: always; 2: never */
     uint32_t reserved;
+    const uint8_t *profile_sample;  /* host bytes for the profiling walk, or NULL */
+    uint64_t profile_bytes;
 } sfa_load_options;
 
 typedef struct sfa_table_info {
@@ -163,7 +172,7 @@ typedef struct sfa_table_info {
     uint32_t next_bytes;     /* width of a walk-table entry: 1, 2 or 4 */
     uint32_t map_bytes;      /* width of a mapping entry: 1, 2 or 4 */
     uint32_t table_in_lds;   /* 1 if the walk table is staged into LDS */
-    uint32_t has_monoid;     /* 1 if the D-SFA product table mul[a][b] is present */
+    uint32_t hot_rows;       /* global-table walk: D-SFA rows staged in LDS (0 = none) */
     uint32_t strides;        /* bit s set: stride-s LDS walk tables are present (s = 1, 2, 4) */
     uint32_t reserved;
     uint64_t device_bytes;   /* bytes used in d_buf */

@@ -53,6 +53,8 @@ struct Layout {
     Image img[3];            // strides 1, 2, 4
     uint64_t total = 0;
     uint64_t next_bytes = 0;
+    uint32_t hot_rows = 0;   // global-table walk: leading rows of sfa_next staged in LDS
+    uint32_t renumbered = 0; // 1: D-SFA ids were renumbered by visit count
 };
 
 inline int stride_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : -1; }

@@ -165,7 +165,56 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
         off = align256(off + bytes);
     }
     L.total = off;
+    const bool any_img = L.img[0].present || L.img[1].present || L.img[2].present;
+    if (d->n_sfa && !any_img) {
+        // global-table walk: stage as many leading rows as the budget holds
+        const uint64_t rb = (uint64_t)L.C * L.next_w;
+        const uint64_t hb = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : lds_limit,
+                                               lds_limit > kWalkExtraLds + 512 ? lds_limit - kWalkExtraLds - 512 : 0);
+        L.hot_rows = (uint32_t)std::min<uint64_t>(d->n_sfa, rb ? hb / rb : 0);
+    }
+    const uint32_t rn = o ? o->renumber : 0;
+    L.renumbered = d->n_sfa > 1 && (rn == 1 || (rn == 0 && !any_img)) ? 1 : 0;
     return L;
+}
+
+// Permutation of D-SFA ids by visit count in a profiling walk (identity
+// stays 0; then descending count, ties by id).  The walk follows the sample
+// bytes (256 walkers over consecutive parts) or, without a sample, classes
+// drawn uniformly (256 walkers x 2048 steps, xorshift generator).
+std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_options *o) {
+    const uint32_t m = d->n_sfa, C = d->n_classes;
+    std::vector<uint64_t> count(m, 0);
+    const uint32_t W = 256;
+    if (o && o->profile_sample && o->profile_bytes) {
+        const uint64_t part = std::max<uint64_t>(1, o->profile_bytes / W);
+        for (uint32_t w = 0; w < W; ++w) {
+            uint32_t s = 0;
+            const uint64_t b0 = (uint64_t)w * part, b1 = std::min<uint64_t>(o->profile_bytes, b0 + part);
+            for (uint64_t i = b0; i < b1; ++i) {
+                s = d->sfa_next[(uint64_t)s * C + d->byte_class[o->profile_sample[i]]];
+                ++count[s];
+            }
+        }
+    } else {
+        uint32_t x = 0x9e3779b9u;
+        for (uint32_t w = 0; w < W; ++w) {
+            uint32_t s = 0;
+            for (uint32_t i = 0; i < 2048; ++i) {
+                x ^= x << 13;
+                x ^= x >> 17;
+                x ^= x << 5;
+                s = d->sfa_next[(uint64_t)s * C + (x % C)];
+                ++count[s];
+            }
+        }
+    }
+    std::vector<uint32_t> ids(m);
+    for (uint32_t i = 0; i < m; ++i) ids[i] = i;
+    std::stable_sort(ids.begin() + 1, ids.end(), [&](uint32_t a, uint32_t b) { return count[a] > count[b]; });
+    std::vector<uint32_t> perm(m);   // old id -> new id
+    for (uint32_t i = 0; i < m; ++i) perm[ids[i]] = i;
+    return perm;
 }
 
 template <typename T>
@@ -173,9 +222,26 @@ void put(std::vector<uint8_t> &img, uint64_t off, uint64_t i, T v) {
     std::memcpy(&img[off + i * sizeof(T)], &v, sizeof(T));
 }
 
-void pack(const sfa_table_desc *d, const Layout &L, std::vector<uint8_t> &img) {
+void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, std::vector<uint8_t> &img) {
     img.assign(L.total, 0);
     const uint32_t C = L.C;
+    // renumbered copies of the D-SFA arrays (new id = perm[old id])
+    sfa_table_desc dd = *d0;
+    std::vector<uint32_t> rnext, rmap;
+    if (L.renumbered) {
+        const std::vector<uint32_t> perm = visit_order(d0, o);
+        const uint32_t m = d0->n_sfa, n = d0->n_dfa;
+        rnext.resize((uint64_t)m * C);
+        rmap.resize((uint64_t)m * n);
+        for (uint32_t s = 0; s < m; ++s) {
+            const uint32_t t = perm[s];
+            for (uint32_t c = 0; c < C; ++c) rnext[(uint64_t)t * C + c] = perm[d0->sfa_next[(uint64_t)s * C + c]];
+            std::memcpy(&rmap[(uint64_t)t * n], &d0->sfa_map[(uint64_t)s * n], sizeof(uint32_t) * n);
+        }
+        dd.sfa_next = rnext.data();
+        dd.sfa_map = rmap.data();
+    }
+    const sfa_table_desc *d = &dd;
     for (int b = 0; b < 256; ++b) {
         put<uint16_t>(img, L.off_cls, b, (uint16_t)(d->byte_class[b] * L.next_w));
         put<uint16_t>(img, L.off_dcls, b, (uint16_t)(d->byte_class[b] * 2));
@@ -256,7 +322,7 @@ extern "C" sfa_status sfa_load_table(const sfa_table_desc *desc, const sfa_load_
     sfa_table *t = new (std::nothrow) sfa_table();
     if (!t) return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
     try {
-        pack(desc, L, t->image);
+        pack(desc, opts, L, t->image);
     } catch (const std::bad_alloc &) {
         delete t;
         return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
@@ -285,7 +351,7 @@ extern "C" sfa_status sfa_table_get_info(const sfa_table *t, sfa_table_info *out
     out->next_bytes = t->L.next_w;
     out->map_bytes = t->L.map_w;
     out->table_in_lds = t->L.img[0].present | t->L.img[1].present | t->L.img[2].present;
-    out->has_monoid = 0;
+    out->hot_rows = t->L.hot_rows;
     out->strides = (t->L.img[0].present ? 2u : 0u) | (t->L.img[1].present ? 4u : 0u) | (t->L.img[2].present ? 16u : 0u);
     out->device_bytes = t->L.total;
     return SFA_OK;
@@ -319,6 +385,7 @@ struct MatchArgs {
     uint32_t map_bytes;      // bytes of the mapping rows
     uint32_t bm_lds;         // 1: the last block stages all block mappings (u16) in LDS
     uint32_t lanes_per_chunk;  // LPC: consecutive lanes sharing one chunk (walk kernels)
+    uint32_t hot_rows;       // global-table walk: rows 0..hot_rows-1 staged in LDS
     const uint16_t *cls;     // global walk / speculative: u16[256] class column offsets
     const uint8_t *img;      // LDS image, global walk table, or u16 DFA table
     const uint8_t *map;      // mapping rows
@@ -647,21 +714,32 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     block_done(a, smem, s_scr, s_flag);
 }
 
-// Global-table walk (tables too large for LDS): stride 1, state ids of
-// width NT, table rows read through L1/L2.
+// Global-table walk (tables too large for an LDS image): stride 1, state
+// ids of width NT.  The table's rows 0..hot_rows-1 (the most visited states,
+// after the loader's renumbering) are staged in LDS; other rows are read
+// through L1/L2.
 template <int K, typename NT>
 __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint16_t *s_cls = (uint16_t *)smem;            // 512 B
-    uint32_t *s_ids = (uint32_t *)(smem + 512);
+    const uint32_t rb = a.row_bytes, H = a.hot_rows;
+    const uint32_t hot_bytes = ((H * rb) + 15) & ~15u;
+    uint8_t *s_hot = smem + 512;
+    uint32_t *s_ids = (uint32_t *)(smem + 512 + hot_bytes);
     uint32_t *s_flag = s_ids + K * kBlock;
     uint32_t *s_scr = s_flag + 4;
     for (uint32_t i = threadIdx.x; i < 256; i += kBlock) s_cls[i] = a.cls[i];
+    {
+        const uint4 *src = (const uint4 *)a.img;
+        uint4 *dst = (uint4 *)s_hot;
+        for (uint32_t i = threadIdx.x; i < hot_bytes / 16; i += kBlock) dst[i] = src[i];
+    }
     __syncthreads();
-    const uint32_t rb = a.row_bytes;
     const uint8_t *__restrict__ tab = a.img;
     auto step = [&](uint32_t s, uint32_t b) -> uint32_t {
-        return *(const NT *)(tab + (size_t)__umul24(s, rb) + s_cls[b]);
+        const uint32_t off = __umul24(s, rb) + s_cls[b];
+        if (s < H) return *(const NT *)(s_hot + off);
+        return *(const NT *)(tab + off);
     };
     uint64_t c0, c1, pos[K], end[K];
     lane_pieces<K, 16, kBlock>(a, c0, c1, pos, end);
@@ -1021,10 +1099,12 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.img = t->d_base + t->L.off_next;
         a.cls = (const uint16_t *)(t->d_base + t->L.off_cls);
         a.row_bytes = t->L.C * t->L.next_w;
-        a.region_bytes = 512;
-        a.map_lds = 0;
+        a.hot_rows = t->L.hot_rows;
+        const uint32_t hot_bytes = ((a.hot_rows * a.row_bytes) + 15) & ~15u;
+        a.region_bytes = 512 + hot_bytes;
+        a.map_lds = a.map_bytes <= a.region_bytes;
         a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * kBlock * 4;
-        const size_t lds = 512 + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        const size_t lds = a.region_bytes + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.blocks, lds, s, a);
         else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.blocks, lds, s, a);

@@ -209,7 +209,7 @@ class GpuBackend:
     """Device side of the server: pinned staging, device pool, batch and single launches."""
 
     def __init__(self, tables, pool_bytes: int = 1 << 30, n_streams: int = 3, piece_bytes: int = 4096,
-                 units_per_lane: int = 2, device=None):
+                 units_per_lane: int = 2, device=None, max_batch_requests: int = 4096, result_slots: int = 64):
         import torch
         from .batch import Batch, BatchOptions
         self.torch = torch
@@ -222,6 +222,10 @@ class GpuBackend:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.next_stream = 0
         self.options = BatchOptions(piece_bytes, 0, units_per_lane)
+        # pinned result slots, reused round robin (more slots than batches in flight)
+        self.result_slots = [torch.empty((max_batch_requests, 2), dtype=torch.int32, pin_memory=True)
+                             for _ in range(result_slots)]
+        self.next_slot = 0
 
     def _stream(self):
         s = self.streams[self.next_stream % len(self.streams)]
@@ -239,8 +243,15 @@ class GpuBackend:
                 self.dev_pool[off:off + total].copy_(self.host_pool[off:off + total], non_blocking=True)
         return total
 
+    def _slot(self, n):
+        buf = self.result_slots[self.next_slot % len(self.result_slots)]
+        self.next_slot += 1
+        return buf[:n]
+
     def launch_batch(self, requests, off):
         torch = self.torch
+        if len(requests) == 1:
+            return self.launch_single(requests[0], off)
         s = self._stream()
         total = self._stage(requests, off, s)
         lens = np.array([r.nbytes for r in requests], dtype=np.int64)
@@ -251,7 +262,7 @@ class GpuBackend:
             b = self.Batch(self.tables, doc_off, jobs, self.options, stream=s)
             data = self.dev_pool[off:off + max(total, 1)]
             out = b.run(data, stream=s)
-            host_out = torch.empty(out.shape, dtype=out.dtype, pin_memory=True)
+            host_out = self._slot(len(requests))
             host_out.copy_(out, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
@@ -265,7 +276,7 @@ class GpuBackend:
         with torch.cuda.stream(s):
             data = self.dev_pool[off:off + request.nbytes]
             out = match(self.tables[request.table], data, stream=s)
-            host_out = torch.empty((1, 2), dtype=out.dtype, pin_memory=True)
+            host_out = self._slot(1)
             host_out.copy_(out.view(1, 2), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
@@ -276,6 +287,10 @@ class GpuBackend:
 
     def results(self, handle):
         return handle[1].numpy().tolist()
+
+
+# The server keeps at most max_inflight launches in flight; result slots are
+# reused round robin, so GpuBackend needs result_slots > max_inflight.
 
 
 class PlainBackend:

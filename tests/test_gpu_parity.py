@@ -186,3 +186,48 @@ def test_workspace_reuse_across_sizes():
     for seed, n in [(1, 1_000_000), (2, 1000), (3, 500_000), (4, 0), (5, 10)]:
         data = W.c1_input(seed, n=n)
         assert run(W.REGEX_C1, data, n_chunks=0) == oracle_result(W.REGEX_C1, data)
+
+
+# --------------------------------------------------------------------------
+# renumbered D-SFA ids and the hot-row global walk
+# --------------------------------------------------------------------------
+def run_table(t, rx, data, n_chunks=0):
+    say(rx[:40], "n=%d" % data.size, "chunks=%d" % n_chunks, "info", t.info)
+    return sfa.match(t, to_device(data), n_chunks=n_chunks).tolist()
+
+
+@pytest.mark.parametrize("rx", [W.REGEX_C1, W.REGEX_C2, "(ab)*", W.rn_regex(7)])
+def test_renumbered_ids_and_hot_rows_keep_results(rx):
+    rng = np.random.default_rng(21)
+    data = (W.c2_input(21, n=300_001) if rx in (W.REGEX_C2, "(ab)*")
+            else W.c1_input(21, n=300_000) if rx == W.REGEX_C1
+            else rng.choice(np.frombuffer(b"0123456789", np.uint8), size=300_000))
+    want = oracle_result(rx, data)
+    c = sfa.compile(rx)
+    # LDS image path with renumbered ids
+    t1 = sfa.load(c, renumber=1)
+    assert run_table(t1, rx, data, 777) == want
+    # global walk, all rows hot
+    t2 = sfa.load(c, force_global=True)
+    assert t2.info["hot_rows"] == c.info.n_sfa
+    assert run_table(t2, rx, data, 777) == want
+    # global walk, only a few rows hot (the rest read from global memory)
+    t3 = sfa.load(c, force_global=True, lds_budget=16)
+    assert 0 < t3.info["hot_rows"] < c.info.n_sfa
+    assert run_table(t3, rx, data, 777) == want
+    # no renumbering at all
+    t4 = sfa.load(c, force_global=True, lds_budget=16, renumber=2)
+    assert run_table(t4, rx, data, 777) == want
+
+
+def test_c3_hot_rows_with_profile_sample():
+    kws = W.c3_keywords(2)
+    rx = W.c3_regex(kws)
+    data = W.c3_input(7, 1 << 24, kws, rate=3e-6)
+    want = oracle_result(rx, data)
+    c = sfa.compile(rx)
+    t = sfa.load(c, profile_sample=data[: 1 << 20])
+    assert 0 < t.info["hot_rows"] < c.info.n_sfa
+    assert run_table(t, rx, data) == want
+    t2 = sfa.load(c)            # profile from uniformly random classes
+    assert run_table(t2, rx, data, 4096) == want

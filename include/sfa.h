@@ -196,10 +196,13 @@ sfa_status sfa_free_table(sfa_table *t);
  *   legal (empty chunks are the identity); n = 0 gives (q0, accept(q0)).
  *   Any alignment of d_in is accepted.
  *
- *   Workspace: sfa_match_workspace_bytes() bytes of device memory, which must
- *   be zero-filled before its first use; each call leaves its control word
- *   zero again, so a workspace is reused without clearing.  Calls sharing a
- *   workspace must not overlap.  d_out receives one sfa_result.
+ *   Workspace: sfa_match_workspace_bytes() bytes of device memory (enough
+ *   for sfa_match, sfa_match_speculative and sfa_match_ex with any plan at
+ *   the same n and n_chunks), which must be zero-filled before its first
+ *   use; each call leaves its control words zero again, so a workspace is
+ *   reused without clearing.  It holds the per-block mappings of the grid
+ *   composition.  Calls sharing a workspace must not overlap.  d_out
+ *   receives one sfa_result.
  * ---------------------------------------------------------------------- */
 sfa_status sfa_match_workspace_bytes(const sfa_table *t, uint64_t n, uint32_t n_chunks,
                                      size_t *out_bytes);

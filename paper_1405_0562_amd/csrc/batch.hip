@@ -405,16 +405,23 @@ extern "C" sfa_status sfa_batch_create(const sfa_table *const *tables, uint32_t 
         put(b->off_docs, docs.data(), sizeof(BDoc) * docs.size());
         put(b->off_jobs, bj.data(), sizeof(BJob) * bj.size());
         put(b->off_gjobs, gj.data(), sizeof(BGroupJob) * gj.size());
-        if (b->lds_tables) {
-            const size_t lds = b->lds_bytes;
-            // allow dynamic LDS above 64 KiB for every instantiation
-            hipFuncSetAttribute((const void *)k_batch_walk<1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipFuncSetAttribute((const void *)k_batch_walk<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipFuncSetAttribute((const void *)k_batch_walk<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        }
     } catch (const std::bad_alloc &) {
         delete b;
         return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
+    }
+    if (b->lds_tables) {
+        // allow dynamic LDS above 64 KiB for every instantiation
+        const int lds = (int)b->lds_bytes;
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch_walk<1, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_batch_walk<2, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_batch_walk<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) {
+            delete b;
+            return sfa_fail(SFA_ERR_HIP, std::string("batch LDS attribute: ") + hipGetErrorString(e));
+        }
     }
     *out = b;
     return SFA_OK;

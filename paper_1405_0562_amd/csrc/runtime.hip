@@ -61,7 +61,9 @@ constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
 constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
 constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K * block threads <= 2048)
 constexpr uint32_t kPairTable = 65536;       // byte-pair class table entries (u8)
-constexpr uint64_t kWsHeader = 256;          // control word area at the start of a workspace
+constexpr uint32_t kSpecStage = 16 * 1024;  // speculative blocks: LDS region for the grid composition
+constexpr uint64_t kWsHeader = 4096;         // workspace control words: [0] top level, [1 + r] level-1 run r
+constexpr uint32_t kMaxRuns = kWsHeader / 4 - 1;
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
@@ -379,21 +381,47 @@ struct MatchArgs {
     uint32_t wide_mul;       // LDS walk, stride 4: C*C (first pair's weight in the column index)
     uint32_t img_bytes;      // LDS walk: image bytes; speculative: DFA table bytes
     uint32_t groups;         // G: groups per block in the block composition
-    uint32_t final_groups;   // G for the grid composition
+    uint32_t groups1;        // G for a level-1 grid composition (one run of super_blocks blocks)
+    uint32_t final_groups;   // G for the top grid composition
     uint32_t region_bytes;   // LDS bytes at offset 0 free once the walk is over (multiple of 16)
     uint32_t map_lds;        // 1: the mapping rows are copied into that region for the block composition
     uint32_t map_bytes;      // bytes of the mapping rows
-    uint32_t bm_lds;         // 1: the last block stages all block mappings (u16) in LDS
+    uint32_t map_stride;     // u16 entries per stored block or group mapping (n_dfa rounded up to 8)
+    uint32_t super_blocks;   // blocks per level-1 run; n_super == 1: one level
+    uint32_t n_super;        // level-1 runs (the top composition composes n_super mappings)
+    uint32_t stage1;         // 1: level-1 compositions stage their block mappings in LDS
+    uint32_t stage2;         // 1: the top composition stages its mappings in LDS
     uint32_t lanes_per_chunk;  // LPC: consecutive lanes sharing one chunk (walk kernels)
     uint32_t hot_rows;       // global-table walk: rows 0..hot_rows-1 staged in LDS
     const uint16_t *cls;     // global walk / speculative: u16[256] class column offsets
     const uint8_t *img;      // LDS image, global walk table, or u16 DFA table
     const uint8_t *map;      // mapping rows
     const uint8_t *accept;   // u8[n_dfa]
-    uint32_t *counter;       // workspace control word
-    uint32_t *block_maps;    // [gridDim.x * n_dfa]
+    uint32_t *counter;       // workspace control words: [0] top, [1 + r] level-1 run r
+    uint16_t *block_maps;    // [gridDim.x * map_stride]
+    uint16_t *group_maps;    // [n_super * map_stride] when n_super > 1
     sfa_result *out;
 };
+
+// Copies n16 16-byte words from global memory to LDS; each thread has U
+// loads in flight before it waits, so the copy costs one memory latency per
+// U * blockDim.x words instead of one per word.
+template <int U = 8>
+__device__ __forceinline__ void copy16(uint4 *dst, const uint4 *__restrict__ src, uint32_t n16) {
+    for (uint32_t base = threadIdx.x; base < n16; base += U * blockDim.x) {
+        uint4 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = base + u * blockDim.x;
+            if (i < n16) r[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = base + u * blockDim.x;
+            if (i < n16) dst[i] = r[u];
+        }
+    }
+}
 
 // Phase 1 of a composition: the elements 0..E-1 (mappings, in text order) are
 // cut into G groups of R consecutive elements; for every (group g, start
@@ -401,9 +429,9 @@ struct MatchArgs {
 // mapping first (reverse composition, f . g = g o f), and the end state is
 // stored at out[g * n + q].  `get(e, x)` is mapping e applied to x.  Four
 // pairs per thread are followed together to hide load latency.
-template <typename Get>
+template <typename Get, typename Out>
 __device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, uint32_t G, uint32_t n,
-                                              uint32_t *out) {
+                                              Out *out) {
     const uint32_t items = G * n;
     for (uint32_t base = threadIdx.x; base < items; base += 4 * blockDim.x) {
         uint32_t it[4], x[4], e0[4], e1[4];
@@ -430,19 +458,16 @@ __device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, u
 }
 
 // Block composition: the block's E piece states (D-SFA ids in text order,
-// s_ids) become the block mapping M[q], written to out_map.  The mapping rows
-// are read from LDS (copied over the walk-table region) when they fit.
+// s_ids) become the block mapping M[q], written to out_map (u16).  The
+// mapping rows are read from LDS (copied over the walk-table region) when
+// they fit.
 template <typename MT>
 __device__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t *s_ids, uint32_t E,
-                              uint32_t *scratch, uint32_t *__restrict__ out_map) {
+                              uint32_t *scratch, uint16_t *__restrict__ out_map) {
     const uint32_t n = a.n_dfa, G = a.groups, R = E / G;
-    uint32_t *target = G == 1 ? nullptr : scratch;
+    uint32_t *target = scratch;
     if (a.map_lds) {
-        {
-            const uint4 *src = (const uint4 *)a.map;
-            uint4 *dst = (uint4 *)smem;
-            for (uint32_t i = threadIdx.x; i < (a.map_bytes + 15) / 16; i += blockDim.x) dst[i] = src[i];
-        }
+        copy16((uint4 *)smem, (const uint4 *)a.map, (a.map_bytes + 15) / 16);
         __syncthreads();
         const MT *m = (const MT *)smem;
         auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[s_ids[e] * n + x]; };
@@ -465,62 +490,95 @@ __device__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t 
     for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
         uint32_t x = q;
         for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
-        out_map[q] = x;
+        out_map[q] = (uint16_t)x;
     }
 }
 
-// Grid-level step run by the last block to finish: composes the block
-// mappings in block order, applies the result to q0 and writes the answer.
-__device__ void finalize_grid(const MatchArgs &a, uint8_t *smem, uint32_t *scratch) {
-    const uint32_t B = gridDim.x, n = a.n_dfa;
-    const uint32_t G = a.final_groups;   // groups of consecutive blocks
-    const uint32_t R = (B + G - 1) / G;
-    const uint32_t *bm = a.block_maps;
-    uint32_t x = a.q0;
-    if (a.bm_lds) {
-        uint16_t *s_bm = (uint16_t *)smem;
-        for (uint32_t i = threadIdx.x; i < B * n; i += blockDim.x) s_bm[i] = (uint16_t)bm[i];
-        __syncthreads();
-        if (G == 1) {
-            if (threadIdx.x == 0)
-                for (uint32_t b = 0; b < B; ++b) x = s_bm[b * n + x];
-        } else {
-            follow_groups([&](uint32_t b, uint32_t y) -> uint32_t { return s_bm[b * n + y]; }, B, R, G, n, scratch);
-        }
-    } else {
-        if (G == 1) {
-            if (threadIdx.x == 0)
-                for (uint32_t b = 0; b < B; ++b) x = bm[(size_t)b * n + x];
-        } else {
-            follow_groups([&](uint32_t b, uint32_t y) -> uint32_t { return bm[(size_t)b * n + y]; }, B, R, G, n,
-                          scratch);
-        }
+// Composition of `count` mappings in text order, `get(e, x)` being mapping e
+// applied to x, in G groups.  With `out` the whole composed mapping is
+// written there (u16); otherwise thread 0 returns its value at q0.
+template <typename Get>
+__device__ uint32_t compose_rows(Get get, uint32_t count, uint32_t G, uint32_t n, uint32_t q0, uint32_t *scratch,
+                                 uint16_t *out) {
+    uint32_t x = q0;
+    if (G == 1) {
+        if (out) follow_groups(get, count, count, 1, n, out);
+        else if (threadIdx.x == 0)
+            for (uint32_t e = 0; e < count; ++e) x = get(e, x);
+        return x;
     }
-    if (G > 1) {
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
+    follow_groups(get, count, (count + G - 1) / G, G, n, scratch);
+    __syncthreads();
+    if (out) {
+        for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
+            uint32_t y = q;
+            for (uint32_t g = 0; g < G; ++g) y = scratch[g * n + y];
+            out[q] = (uint16_t)y;
+        }
+    } else if (threadIdx.x == 0) {
+        for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
     }
+    return x;
+}
+
+// Composes `count` stored mappings (u16 rows of a.map_stride entries, text
+// order) starting at src; staged: the rows are first copied to LDS offset 0.
+__device__ uint32_t compose_stored(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, const uint16_t *src,
+                                   uint32_t count, uint32_t G, uint32_t staged, uint16_t *out) {
+    const uint32_t n = a.n_dfa, ns = a.map_stride;
+    if (staged) {
+        copy16((uint4 *)smem, (const uint4 *)src, count * ns / 8);
+        __syncthreads();
+        const uint16_t *m = (const uint16_t *)smem;
+        return compose_rows([&](uint32_t e, uint32_t y) -> uint32_t { return m[e * ns + y]; }, count, G, n, a.q0,
+                            scratch, out);
+    }
+    const uint16_t *__restrict__ m = src;
+    return compose_rows([&](uint32_t e, uint32_t y) -> uint32_t { return m[(size_t)e * ns + y]; }, count, G, n,
+                        a.q0, scratch, out);
+}
+
+// Counts this block's arrival at a counter that wraps back to zero after
+// `count` arrivals (atomicInc limit).  True in the last block to arrive,
+// which then sees every earlier block's stores (release before the count,
+// acquire after it).  s_last is one LDS word used for nothing else.
+__device__ bool arrive(uint32_t *counter, uint32_t count, uint32_t *s_last) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicInc(counter, count - 1);
+        *s_last = (prev == count - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!*s_last) return false;
+    __threadfence();
+    return true;
+}
+
+// Grid composition, after this block stored its mapping in block_maps.  One
+// level: the last block to finish composes all block mappings in block order
+// and applies the result to q0.  Two levels: the last block of each run of
+// super_blocks consecutive blocks composes the run into a group mapping, and
+// the last run to finish composes the group mappings.
+__device__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, uint32_t *s_last) {
+    const uint32_t B = gridDim.x;
+    const uint16_t *top = a.block_maps;
+    uint32_t top_count = B;
+    if (a.n_super > 1) {
+        const uint32_t r = blockIdx.x / a.super_blocks, first = r * a.super_blocks;
+        const uint32_t count = min(a.super_blocks, B - first);
+        if (!arrive(a.counter + 1 + r, count, s_last)) return;
+        compose_stored(a, smem, scratch, a.block_maps + (size_t)first * a.map_stride, count, a.groups1, a.stage1,
+                       a.group_maps + (size_t)r * a.map_stride);
+        top = a.group_maps;
+        top_count = a.n_super;
+    }
+    if (!arrive(a.counter, top_count, s_last)) return;
+    const uint32_t x = compose_stored(a, smem, scratch, top, top_count, a.final_groups, a.stage2, nullptr);
     if (threadIdx.x == 0) {
         a.out->state = x;
         a.out->accept = a.accept[x];
     }
-}
-
-// Publish this block's mapping and let the last block compose the grid.
-// s_last is one LDS word used for nothing else.
-__device__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, uint32_t *s_last) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // wraps to 0 after gridDim.x increments, leaving the word zero again
-        const uint32_t prev = atomicInc(a.counter, gridDim.x - 1);
-        *s_last = (prev == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!*s_last) return;
-    __threadfence();
-    finalize_grid(a, smem, scratch);
 }
 
 __device__ __forceinline__ uint32_t word_of(const uint4 &v, int d) {
@@ -567,11 +625,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     uint32_t *s_ids = (uint32_t *)(smem + img);
     uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
-    {
-        const uint4 *src = (const uint4 *)a.img;
-        uint4 *dst = (uint4 *)smem;
-        for (uint32_t i = threadIdx.x; i < img / 16; i += TB) dst[i] = src[i];
-    }
+    copy16((uint4 *)smem, (const uint4 *)a.img, img / 16);
     __syncthreads();
 
     const uint32_t one = a.one_off, wide = a.wide_mul;
@@ -706,7 +760,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k] / rs;
     __syncthreads();   // the walk is over: the image region may be reused
     const uint32_t E = K * TB;
-    uint32_t *bmap = a.block_maps + (size_t)blockIdx.x * a.n_dfa;
+    uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
     if (a.n_dfa <= 256)
         compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
     else
@@ -729,11 +783,7 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
     uint32_t *s_flag = s_ids + K * kBlock;
     uint32_t *s_scr = s_flag + 4;
     for (uint32_t i = threadIdx.x; i < 256; i += kBlock) s_cls[i] = a.cls[i];
-    {
-        const uint4 *src = (const uint4 *)a.img;
-        uint4 *dst = (uint4 *)s_hot;
-        for (uint32_t i = threadIdx.x; i < hot_bytes / 16; i += kBlock) dst[i] = src[i];
-    }
+    copy16((uint4 *)s_hot, (const uint4 *)a.img, hot_bytes / 16);
     __syncthreads();
     const uint8_t *__restrict__ tab = a.img;
     auto step = [&](uint32_t s, uint32_t b) -> uint32_t {
@@ -803,7 +853,7 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k];
     __syncthreads();
     const uint32_t E = K * kBlock;
-    uint32_t *bmap = a.block_maps + (size_t)blockIdx.x * a.n_dfa;
+    uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
     if (a.n_dfa <= 256)
         compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
     else
@@ -820,14 +870,10 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
     uint16_t *s_cls = (uint16_t *)smem;                        // 512 B
     uint16_t *s_dn = (uint16_t *)(smem + 512);                 // u16 [n_dfa * C]
     const uint32_t dn_bytes = (a.img_bytes + 15) & ~15u;
-    uint32_t *s_flag = (uint32_t *)(smem + 512 + dn_bytes);
+    uint32_t *s_flag = (uint32_t *)(smem + a.region_bytes);   // region_bytes >= 512 + dn_bytes
     uint32_t *s_T = s_flag + 4;                                // [4][n_dfa]
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) s_cls[i] = a.cls[i];
-    {
-        const uint4 *src = (const uint4 *)a.img;
-        uint4 *dst = (uint4 *)s_dn;
-        for (uint32_t i = threadIdx.x; i < dn_bytes / 16; i += blockDim.x) dst[i] = src[i];
-    }
+    copy16((uint4 *)s_dn, (const uint4 *)a.img, dn_bytes / 16);
     __syncthreads();
     const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const uint32_t n = a.n_dfa, rb = a.row_bytes;
@@ -868,11 +914,11 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
         if (q < n) s_T[wave * n + q] = T[s];
     }
     __syncthreads();
-    uint32_t *bm = a.block_maps + (size_t)blockIdx.x * n;
+    uint16_t *bm = a.block_maps + (size_t)blockIdx.x * a.map_stride;
     for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
         uint32_t x = q;
         for (uint32_t w = 0; w < kSpecWaves; ++w) x = s_T[w * n + x];
-        bm[q] = x;
+        bm[q] = (uint16_t)x;
     }
     block_done(a, smem, s_T, s_flag);
 }
@@ -896,9 +942,12 @@ bool lds_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
 }
 
 struct Plan {
-    uint32_t n_chunks = 0, blocks = 0, S = 0, K = 1, G = 16, D = 2, TB = kBlock, LPC = 1, groups = 1, final_groups = 1;
+    uint32_t n_chunks = 0, blocks = 0, S = 0, K = 1, G = 16, D = 2, TB = kBlock, LPC = 1, groups = 1;
     uint64_t chunk_len = 0;
-    size_t ws_bytes = 0;
+    // grid composition
+    uint32_t stage_bytes = 0;   // LDS at offset 0 the finishing blocks may use for staging
+    uint32_t map_stride = 0, super_blocks = 0, n_super = 1, groups1 = 1, final_groups = 1, stage1 = 0, stage2 = 0;
+    size_t ws_maps = 0, ws_groups = 0, ws_bytes = 0;   // workspace offsets and size
 };
 
 // Groups for a composition of E elements: about sqrt(E) groups, so that the
@@ -910,6 +959,48 @@ uint32_t pick_groups(uint32_t E, uint32_t n_dfa) {
            (uint64_t)G * 2 * n_dfa <= 4096)
         G *= 2;
     return G;
+}
+
+// LDS bytes at offset 0 that a kernel no longer needs once its walk and
+// block composition are over, usable by the grid composition for staging.
+uint32_t spec_region(const sfa_table *t) {
+    return std::max<uint32_t>(512 + ((2 * t->L.n_dfa * t->L.C + 15) & ~15u), kSpecStage);
+}
+
+uint32_t stage_bytes(const sfa_table *t, const Plan &P, bool speculative) {
+    if (speculative) return spec_region(t);
+    const uint32_t ids = P.K * P.TB * 4;
+    if (P.S) return ((t->L.img[stride_index(P.S)].bytes + 15) & ~15u) + ids;
+    const uint32_t row_bytes = t->L.C * t->L.next_w;
+    return 512 + ((t->L.hot_rows * row_bytes + 15) & ~15u) + ids;
+}
+
+// Grid composition plan: one level when all block mappings fit the staging
+// LDS at once, else runs of super_blocks blocks composed by the last block
+// of each run, then the run mappings by the last run.  A level whose
+// mappings do not fit reads them from global memory instead.  The control
+// words sit in a fixed area at the start of every workspace that no other
+// write touches, so workspaces are shared by calls with different plans.
+void plan_grid(Plan &P, uint32_t n_dfa) {
+    const uint32_t B = P.blocks;
+    P.map_stride = (n_dfa + 7) & ~7u;
+    const uint32_t fit = P.stage_bytes / (P.map_stride * 2);   // mappings that fit in the staging LDS
+    const uint32_t run = std::max(fit, 1u);
+    if (B <= run) {
+        P.super_blocks = B;
+        P.n_super = 1;
+        P.stage2 = B <= fit;
+    } else {
+        P.super_blocks = std::max(run, (B + kMaxRuns - 1) / kMaxRuns);
+        P.n_super = (B + P.super_blocks - 1) / P.super_blocks;
+        P.stage1 = P.super_blocks <= fit;
+        P.stage2 = P.n_super <= fit;
+        P.groups1 = pick_groups(P.super_blocks, n_dfa);
+    }
+    P.final_groups = pick_groups(P.n_super > 1 ? P.n_super : B, n_dfa);
+    P.ws_maps = kWsHeader;
+    P.ws_groups = P.ws_maps + align256((uint64_t)B * P.map_stride * 2);
+    P.ws_bytes = P.ws_groups + (P.n_super > 1 ? (size_t)P.n_super * P.map_stride * 2 : 0);
 }
 
 sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool speculative, const sfa_plan *user,
@@ -977,8 +1068,8 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         P.blocks = (uint32_t)(((uint64_t)P.n_chunks * LPC + TB - 1) / TB);
         P.groups = pick_groups(P.K * TB, t->L.n_dfa);
     }
-    P.final_groups = pick_groups(P.blocks, t->L.n_dfa);
-    P.ws_bytes = kWsHeader + (size_t)P.blocks * t->L.n_dfa * 4;
+    P.stage_bytes = stage_bytes(t, P, speculative);
+    plan_grid(P, t->L.n_dfa);
     return SFA_OK;
 }
 
@@ -1034,20 +1125,27 @@ MatchArgs base_args(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d
     a.n_dfa = t->L.n_dfa;
     a.q0 = t->L.q0;
     a.groups = P.groups;
+    a.groups1 = P.groups1;
     a.final_groups = P.final_groups;
+    a.map_stride = P.map_stride;
+    a.super_blocks = P.super_blocks;
+    a.n_super = P.n_super;
+    a.stage1 = P.stage1;
+    a.stage2 = P.stage2;
     a.lanes_per_chunk = P.LPC;
     a.accept = t->d_base + t->L.off_acc;
     a.map = t->d_base + t->L.off_map;
     a.map_bytes = (uint32_t)std::min<uint64_t>(UINT32_MAX, (uint64_t)t->L.map_w * t->L.n_sfa * t->L.n_dfa);
     a.counter = (uint32_t *)d_ws;
-    a.block_maps = (uint32_t *)((uint8_t *)d_ws + kWsHeader);
+    a.block_maps = (uint16_t *)((uint8_t *)d_ws + P.ws_maps);
+    a.group_maps = (uint16_t *)((uint8_t *)d_ws + P.ws_groups);
     a.out = d_out;
     return a;
 }
 
 size_t scratch_lds(const Plan &P, uint32_t n_dfa) {
-    return std::max<size_t>(P.groups > 1 ? (size_t)P.groups * n_dfa * 4 : 0,
-                            P.final_groups > 1 ? (size_t)P.final_groups * n_dfa * 4 : 0);
+    const uint32_t G = std::max({P.groups, P.final_groups, P.n_super > 1 ? P.groups1 : 1u});
+    return G > 1 ? (size_t)G * n_dfa * 4 : 0;
 }
 
 }  // namespace
@@ -1057,11 +1155,17 @@ extern "C" sfa_status sfa_match_workspace_bytes(const sfa_table *t, uint64_t n, 
     Plan a, b;
     sfa_status st = make_plan(t, n, n_chunks, true, nullptr, b);
     if (st != SFA_OK) return st;
+    size_t bound = b.ws_bytes;
     if (t->L.n_sfa) {
         st = make_plan(t, n, n_chunks, false, nullptr, a);
         if (st != SFA_OK) return st;
+        // any launch plan: at most 16 lanes per chunk in blocks of >= 256 lanes,
+        // and at most one level-1 run mapping per block
+        const uint64_t B = ((uint64_t)a.n_chunks * 16 + 255) / 256;
+        const uint64_t ms = ((uint64_t)t->L.n_dfa + 7) & ~7ull;
+        bound = std::max<size_t>(bound, kWsHeader + align256(B * ms * 2) + B * ms * 2);
     }
-    *out_bytes = std::max(a.ws_bytes, b.ws_bytes);
+    *out_bytes = std::max(a.ws_bytes, bound);
     return SFA_OK;
 }
 
@@ -1087,7 +1191,6 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.wide_mul = t->L.C * t->L.C;
         a.region_bytes = (im.bytes + 15) & ~15u;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * P.TB * 4;
         const size_t lds = a.region_bytes + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         switch (P.S) {
@@ -1103,7 +1206,6 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         const uint32_t hot_bytes = ((a.hot_rows * a.row_bytes) + 15) & ~15u;
         a.region_bytes = 512 + hot_bytes;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        a.bm_lds = (uint64_t)P.blocks * t->L.n_dfa * 2 <= a.region_bytes + (uint64_t)P.K * kBlock * 4;
         const size_t lds = a.region_bytes + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.blocks, lds, s, a);
@@ -1133,12 +1235,9 @@ extern "C" sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d
     a.cls = (const uint16_t *)(t->d_base + t->L.off_dcls);
     a.img = t->d_base + t->L.off_dnext;
     const uint32_t nd = t->L.n_dfa;
-    a.region_bytes = 512 + ((a.img_bytes + 15) & ~15u);
+    a.region_bytes = spec_region(t);
     a.map_lds = 0;
-    a.bm_lds = (uint64_t)P.blocks * nd * 2 <= a.region_bytes;
-    const size_t lds = 512 + ((a.img_bytes + 15) & ~15u) + 16 +
-                       std::max<size_t>((size_t)kSpecWaves * nd * 4,
-                                        P.final_groups > 1 ? (size_t)P.final_groups * nd * 4 : 0);
+    const size_t lds = a.region_bytes + 16 + std::max<size_t>((size_t)kSpecWaves * nd * 4, scratch_lds(P, nd));
     if (lds > t->lds_per_block)
         return sfa_fail(SFA_ERR_INVALID_ARG, "DFA too large for the speculative kernel's LDS plan");
     const uint32_t S = (nd + 63) / 64;

@@ -231,3 +231,37 @@ def test_c3_hot_rows_with_profile_sample():
     assert run_table(t, rx, data) == want
     t2 = sfa.load(c)            # profile from uniformly random classes
     assert run_table(t2, rx, data, 4096) == want
+
+
+# --------------------------------------------------------------------------
+# grid composition: one level, two levels, top level read from global memory
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n_chunks", [1 << 16, (1 << 20) + 3, 1 << 22])
+def test_many_blocks_two_level_grid_composition(n_chunks):
+    # 2^20 chunks of the LDS walk are 4096 blocks: more block mappings than
+    # one block's LDS holds, so runs of blocks are composed first
+    data = W.c2_input(12, n=(1 << 22) + 1001)
+    check(W.REGEX_C2, data, n_chunks=n_chunks)
+    check(W.REGEX_C2, data, n_chunks=n_chunks, force_global=True)
+    check(W.REGEX_C2, data, n_chunks=n_chunks, speculative=True)
+
+
+def test_speculative_c3_many_chunks_global_top_level():
+    # 65,536 speculative chunks of a ~130-state DFA: 16,384 block mappings in
+    # runs of ~60, whose ~270 run mappings exceed the staging LDS
+    kws = W.c3_keywords(0)
+    rx = W.c3_regex(kws)
+    data = W.c3_input(8, 1 << 23, kws, rate=4e-6)
+    check(rx, data, n_chunks=65536, speculative=True)
+    check(rx, data, n_chunks=65536)
+
+
+def test_workspace_shared_by_one_and_two_level_plans():
+    # calls with different grid plans share one cached workspace: the control
+    # words must stay zero between them whatever the previous plan wrote
+    data = W.c2_input(13, n=(1 << 22) + 77)
+    want = oracle_result(W.REGEX_C2, data)
+    x = to_device(data)
+    for n_chunks, spec in [(65536, False), (65536, True), (1 << 20, False), (4096, True), (7, False),
+                           (1 << 22, False), (65536, True), (0, False), (1 << 20, True)]:
+        assert run(W.REGEX_C2, data, n_chunks=n_chunks, speculative=spec, x=x) == want, (n_chunks, spec)

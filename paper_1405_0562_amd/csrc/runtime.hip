@@ -405,21 +405,24 @@ struct MatchArgs {
 
 // Copies n16 16-byte words from global memory to LDS; each thread has U
 // loads in flight before it waits, so the copy costs one memory latency per
-// U * blockDim.x words instead of one per word.
+// U * blockDim.x words instead of one per word.  Indices past the end are
+// clamped to the last word (a repeated copy of the same value), which keeps
+// the loads unconditional and the staging array in registers.  The copy
+// starts at word `rot` (mod n16), so blocks that stage the same table at the
+// same time spread their requests over different memory channels.
 template <int U = 8>
-__device__ __forceinline__ void copy16(uint4 *dst, const uint4 *__restrict__ src, uint32_t n16) {
+__device__ __forceinline__ void copy16(uint4 *dst, const uint4 *__restrict__ src, uint32_t n16, uint32_t rot = 0) {
     for (uint32_t base = threadIdx.x; base < n16; base += U * blockDim.x) {
         uint4 r[U];
+        uint32_t j[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = base + u * blockDim.x;
-            if (i < n16) r[u] = src[i];
+            const uint32_t i = min(base + u * blockDim.x, n16 - 1) + rot;
+            j[u] = i >= n16 ? i - n16 : i;
+            r[u] = src[j[u]];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t i = base + u * blockDim.x;
-            if (i < n16) dst[i] = r[u];
-        }
+        for (int u = 0; u < U; ++u) dst[j[u]] = r[u];
     }
 }
 
@@ -538,20 +541,31 @@ __device__ uint32_t compose_stored(const MatchArgs &a, uint8_t *smem, uint32_t *
                         a.q0, scratch, out);
 }
 
+// s_waitcnt immediate that waits for vmcnt(0) only (gfx9 encoding: expcnt
+// and lgkmcnt fields left at their maxima).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // Counts this block's arrival at a counter that wraps back to zero after
 // `count` arrivals (atomicInc limit).  True in the last block to arrive,
-// which then sees every earlier block's stores (release before the count,
-// acquire after it).  s_last is one LDS word used for nothing else.
+// which then sees every earlier block's stores.  Publication: every wave
+// waits until its own stores are acknowledged by the L2, then one wave
+// issues the agent-scope release (an L2 write-back) before the count; a
+// release in every wave would write the L2 back once per wave.  The last
+// block takes an agent-scope acquire.  s_last is one LDS word used for
+// nothing else.
 __device__ bool arrive(uint32_t *counter, uint32_t count, uint32_t *s_last) {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicInc(counter, count - 1);
-        *s_last = (prev == count - 1) ? 1u : 0u;
+    if (threadIdx.x < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) {
+            const uint32_t prev = atomicInc(counter, count - 1);
+            *s_last = (prev == count - 1) ? 1u : 0u;
+        }
     }
     __syncthreads();
     if (!*s_last) return false;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
@@ -625,7 +639,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     uint32_t *s_ids = (uint32_t *)(smem + img);
     uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
-    copy16((uint4 *)smem, (const uint4 *)a.img, img / 16);
+    copy16((uint4 *)smem, (const uint4 *)a.img, img / 16, (blockIdx.x * 613u) % (img / 16));
     __syncthreads();
 
     const uint32_t one = a.one_off, wide = a.wide_mul;

@@ -152,6 +152,15 @@ sfa_status sfa_compiled_desc(const sfa_compiled *c, sfa_table_desc *out);
  *   walk over profile_sample (host bytes like the input) or, without a
  *   sample, over uniformly random byte classes.  Renumbering changes only
  *   internal ids: results are DFA states and never depend on it.
+ *   Product table: the D-SFA states are closed under reverse composition
+ *   (f_u . f_v = f_uv, Lemma 1 in Section 4.3; they form the monoid of
+ *   Section 7.1), so for a D-SFA of at most 128
+ *   states the loader tabulates mul[a][b] = the id of f_a . f_b and the
+ *   matchers compose chunk results as state ids (one table lookup per
+ *   composition) instead of as mappings (n_dfa lookups).  It is built only
+ *   when every state is reachable from the identity and the mapping rows
+ *   agree with the transitions (sfa_map[sfa_next[s][c]] equals sfa_map[s]
+ *   followed by the DFA transition on class c); no_product = 1 skips it.
  *   sfa_free_table frees the host handle only; the caller frees d_buf after
  *   work that uses it has finished.
  * ---------------------------------------------------------------------- */
@@ -162,7 +171,7 @@ typedef struct sfa_load_options {
     uint32_t lds_budget;     /* bytes of LDS the walk table (or its hot rows) may take; 0 = default */
     uint32_t renumber;       /* 0: renumber states by visit count when the table is walked from
                                 global memory; 1: always; 2: never */
-    uint32_t reserved;
+    uint32_t no_product;     /* 1: do not build the product table (compositions use the mappings) */
     const uint8_t *profile_sample;  /* host bytes for the profiling walk, or NULL */
     uint64_t profile_bytes;
 } sfa_load_options;
@@ -174,7 +183,7 @@ typedef struct sfa_table_info {
     uint32_t table_in_lds;   /* 1 if the walk table is staged into LDS */
     uint32_t hot_rows;       /* global-table walk: D-SFA rows staged in LDS (0 = none) */
     uint32_t strides;        /* bit s set: stride-s LDS walk tables are present (s = 1, 2, 4) */
-    uint32_t reserved;
+    uint32_t product_table;  /* 1: compositions reduce D-SFA ids through the product table */
     uint64_t device_bytes;   /* bytes used in d_buf */
 } sfa_table_info;
 

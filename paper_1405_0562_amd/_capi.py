@@ -48,7 +48,7 @@ class TableDesc(ctypes.Structure):
 
 class LoadOptions(ctypes.Structure):
     _fields_ = [("force_global", ctypes.c_uint32), ("lds_budget", ctypes.c_uint32),
-                ("renumber", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("renumber", ctypes.c_uint32), ("no_product", ctypes.c_uint32),
                 ("profile_sample", ctypes.c_void_p), ("profile_bytes", ctypes.c_uint64)]
 
 
@@ -56,7 +56,7 @@ class TableInfo(ctypes.Structure):
     _fields_ = [("n_dfa", ctypes.c_uint32), ("n_sfa", ctypes.c_uint32), ("n_classes", ctypes.c_uint32),
                 ("q0", ctypes.c_uint32), ("next_bytes", ctypes.c_uint32), ("map_bytes", ctypes.c_uint32),
                 ("table_in_lds", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
-                ("strides", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("strides", ctypes.c_uint32), ("product_table", ctypes.c_uint32),
                 ("device_bytes", ctypes.c_uint64)]
 
 

@@ -50,6 +50,8 @@ struct Layout {
     uint64_t off_dnext = 0;  // u16[n_dfa * C]
     uint64_t off_next = 0;   // next_w bytes [n_sfa * C]: state ids (global-table walk)
     uint64_t off_map = 0;    // map_w bytes [n_sfa * n_dfa]
+    uint64_t off_mul = 0;    // u8[n_sfa * n_sfa]: product table, id of f_a . f_b (when mul_bytes > 0)
+    uint32_t mul_bytes = 0;  // 0: no product table (compositions go through the mappings)
     Image img[3];            // strides 1, 2, 4
     uint64_t total = 0;
     uint64_t next_bytes = 0;

@@ -62,6 +62,8 @@ constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the co
 constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K * block threads <= 2048)
 constexpr uint32_t kPairTable = 65536;       // byte-pair class table entries (u8)
 constexpr uint32_t kSpecStage = 16 * 1024;  // speculative blocks: LDS region for the grid composition
+constexpr uint32_t kMulMax = 16 * 1024;      // product table bytes at most (u8 ids: n_sfa <= 128)
+constexpr uint32_t kIdRun = 4096;            // product mode: blocks per level-1 run
 constexpr uint64_t kWsHeader = 4096;         // workspace control words: [0] top level, [1 + r] level-1 run r
 constexpr uint32_t kMaxRuns = kWsHeader / 4 - 1;
 
@@ -119,6 +121,35 @@ uint64_t ipow(uint64_t b, uint32_t e) {
     return r;
 }
 
+// True when the product table is well defined for d: every D-SFA state is
+// reachable from the identity (state 0), and the mapping rows agree with the
+// transitions, sfa_map[sfa_next[s][c]][q] = dfa_next[sfa_map[s][q]][c], so
+// that state ids compose like the mappings they stand for (Lemma 1).
+bool product_defined(const sfa_table_desc *d) {
+    const uint32_t m = d->n_sfa, C = d->n_classes, n = d->n_dfa;
+    if (m == 0 || (uint64_t)m * C * n > (1u << 24)) return false;
+    std::vector<uint8_t> seen(m, 0);
+    std::vector<uint32_t> order{0};
+    seen[0] = 1;
+    for (size_t h = 0; h < order.size(); ++h)
+        for (uint32_t c = 0; c < C; ++c) {
+            const uint32_t t = d->sfa_next[(uint64_t)order[h] * C + c];
+            if (!seen[t]) {
+                seen[t] = 1;
+                order.push_back(t);
+            }
+        }
+    if (order.size() != m) return false;
+    for (uint32_t s = 0; s < m; ++s)
+        for (uint32_t c = 0; c < C; ++c) {
+            const uint32_t *to = d->sfa_map + (uint64_t)d->sfa_next[(uint64_t)s * C + c] * n;
+            const uint32_t *from = d->sfa_map + (uint64_t)s * n;
+            for (uint32_t x = 0; x < n; ++x)
+                if (to[x] != d->dfa_next[(uint64_t)from[x] * C + c]) return false;
+        }
+    return true;
+}
+
 // LDS bytes the walk kernel needs besides the image: piece states + scratch.
 constexpr uint32_t kWalkExtraLds = kMaxIds * 4 + 16 + kScratchLds;
 
@@ -145,9 +176,15 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
     off = align256(off + L.next_bytes);
     L.off_map = off;
     off = align256(off + (uint64_t)L.map_w * d->n_sfa * d->n_dfa);
+    if (!(o && o->no_product) && (uint64_t)d->n_sfa * d->n_sfa <= kMulMax && product_defined(d)) {
+        L.off_mul = off;
+        L.mul_bytes = d->n_sfa * d->n_sfa;
+        off = align256(off + L.mul_bytes);
+    }
+    const uint32_t extra = kWalkExtraLds + ((L.mul_bytes + 15) & ~15u);
     const bool allow_lds = d->n_sfa && !(o && o->force_global);
     const uint64_t budget = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : kDefaultLdsBudget + kPairTable,
-                                               lds_limit > kWalkExtraLds ? lds_limit - kWalkExtraLds : 0);
+                                               lds_limit > extra ? lds_limit - extra : 0);
     for (uint32_t S : {1u, 2u, 4u}) {
         Image &im = L.img[stride_index(S)];
         if (!allow_lds) continue;
@@ -172,7 +209,7 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
         // global-table walk: stage as many leading rows as the budget holds
         const uint64_t rb = (uint64_t)L.C * L.next_w;
         const uint64_t hb = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : lds_limit,
-                                               lds_limit > kWalkExtraLds + 512 ? lds_limit - kWalkExtraLds - 512 : 0);
+                                               lds_limit > extra + 512 ? lds_limit - extra - 512 : 0);
         L.hot_rows = (uint32_t)std::min<uint64_t>(d->n_sfa, rb ? hb / rb : 0);
     }
     const uint32_t rn = o ? o->renumber : 0;
@@ -261,6 +298,31 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
         uint32_t v = d->sfa_map[i];
         if (L.map_w == 1) put<uint8_t>(img, L.off_map, i, (uint8_t)v);
         else put<uint16_t>(img, L.off_map, i, (uint16_t)v);
+    }
+    if (L.mul_bytes) {
+        // breadth-first tree from the identity: parent of each state and the
+        // class on the edge into it; then f_a . f_b = delta_s(f_a . f_parent(b),
+        // class into b), filled in breadth-first order of b
+        const uint32_t m = d->n_sfa;
+        std::vector<uint32_t> order{0}, par(m, UINT32_MAX), pcls(m, 0);
+        par[0] = 0;
+        for (size_t h = 0; h < order.size(); ++h)
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t t = d->sfa_next[(uint64_t)order[h] * C + c];
+                if (par[t] == UINT32_MAX) {
+                    par[t] = order[h];
+                    pcls[t] = c;
+                    order.push_back(t);
+                }
+            }
+        for (uint32_t a = 0; a < m; ++a) {
+            uint8_t *row = &img[L.off_mul + (uint64_t)a * m];
+            row[0] = (uint8_t)a;
+            for (size_t h = 1; h < order.size(); ++h) {
+                const uint32_t b = order[h];
+                row[b] = (uint8_t)d->sfa_next[(uint64_t)row[par[b]] * C + pcls[b]];
+            }
+        }
     }
     for (uint32_t S : {1u, 2u, 4u}) {
         const Image &im = L.img[stride_index(S)];
@@ -355,6 +417,7 @@ extern "C" sfa_status sfa_table_get_info(const sfa_table *t, sfa_table_info *out
     out->table_in_lds = t->L.img[0].present | t->L.img[1].present | t->L.img[2].present;
     out->hot_rows = t->L.hot_rows;
     out->strides = (t->L.img[0].present ? 2u : 0u) | (t->L.img[1].present ? 4u : 0u) | (t->L.img[2].present ? 16u : 0u);
+    out->product_table = t->L.mul_bytes ? 1u : 0u;
     out->device_bytes = t->L.total;
     return SFA_OK;
 }
@@ -400,6 +463,11 @@ struct MatchArgs {
     uint32_t *counter;       // workspace control words: [0] top, [1 + r] level-1 run r
     uint16_t *block_maps;    // [gridDim.x * map_stride]
     uint16_t *group_maps;    // [n_super * map_stride] when n_super > 1
+    const uint8_t *mul;      // product table u8[n_sfa * n_sfa] (product mode), else null
+    uint32_t n_sfa;
+    uint32_t mul_lds;        // LDS bytes of the product table copy (multiple of 16); 0: mapping mode
+    uint32_t *block_ids;     // product mode: [gridDim.x] block products
+    uint32_t *run_ids;       // product mode: [n_super] run products
     sfa_result *out;
 };
 
@@ -595,6 +663,81 @@ __device__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch,
     }
 }
 
+// ---- product mode: chunk results composed as D-SFA ids ------------------
+// mul (LDS) is the n_sfa x n_sfa product table: mul[a * ns + b] is the id
+// of f_a . f_b.  Id 0 is the identity f_I, so padding with 0 is harmless.
+
+// Ordered product x_0 . x_1 . ... . x_63 of the ids held by a wave's lanes
+// (lane order = text order).  Butterfly: at distance o the lane whose bit o
+// is clear holds the left operand; every lane ends with the whole product.
+__device__ __forceinline__ uint32_t wave_product(uint32_t x, const uint8_t *mul, uint32_t ns) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_xor((int)x, o, 64);
+        const bool hi = (lane & (uint32_t)o) != 0;
+        x = mul[(hi ? y : x) * ns + (hi ? x : y)];
+    }
+    return x;
+}
+
+// Ordered product of the ids held by the block's threads (thread order);
+// the result is valid in thread 0.  s_w: one LDS word per wave.
+__device__ uint32_t block_product(uint32_t x, const uint8_t *mul, uint32_t ns, uint32_t *s_w) {
+    x = wave_product(x, mul, ns);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x / 64] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        x = s_w[0];
+        for (uint32_t w = 1; w < blockDim.x / 64; ++w) x = mul[x * ns + s_w[w]];
+    }
+    return x;
+}
+
+// Ordered product of ids[0 .. count) (global memory); thread t takes a run
+// of consecutive ids.  Valid in thread 0.
+__device__ uint32_t product_of_ids(const uint32_t *ids, uint32_t count, const uint8_t *mul, uint32_t ns,
+                                   uint32_t *s_w) {
+    const uint32_t c = (count + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = min(count, threadIdx.x * c), b1 = min(count, b0 + c);
+    uint32_t x = 0;
+    for (uint32_t i = b0; i < b1; i += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ids[min(i + u, b1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x = i + u < b1 ? mul[x * ns + v[u]] : x;
+    }
+    return block_product(x, mul, ns, s_w);
+}
+
+// Grid step of product mode, after block_product (x valid in thread 0): as
+// block_done, with one id per block or run instead of a mapping; the last
+// block applies the final D-SFA state's mapping to q0.
+__device__ void finish_ids(const MatchArgs &a, uint32_t x, const uint8_t *mul, uint32_t *s_w, uint32_t *s_last) {
+    const uint32_t B = gridDim.x, ns = a.n_sfa;
+    if (threadIdx.x == 0) a.block_ids[blockIdx.x] = x;
+    const uint32_t *top = a.block_ids;
+    uint32_t top_count = B;
+    if (a.n_super > 1) {
+        const uint32_t r = blockIdx.x / a.super_blocks, first = r * a.super_blocks;
+        const uint32_t count = min(a.super_blocks, B - first);
+        if (!arrive(a.counter + 1 + r, count, s_last)) return;
+        const uint32_t y = product_of_ids(a.block_ids + first, count, mul, ns, s_w);
+        if (threadIdx.x == 0) a.run_ids[r] = y;
+        top = a.run_ids;
+        top_count = a.n_super;
+    }
+    if (!arrive(a.counter, top_count, s_last)) return;
+    const uint32_t f = product_of_ids(top, top_count, mul, ns, s_w);
+    if (threadIdx.x == 0) {
+        const size_t at = (size_t)f * a.n_dfa + a.q0;
+        const uint32_t q = a.n_dfa <= 256 ? a.map[at] : ((const uint16_t *)a.map)[at];
+        a.out->state = q;
+        a.out->accept = a.accept[q];
+    }
+}
+
 __device__ __forceinline__ uint32_t word_of(const uint4 &v, int d) {
     return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
 }
@@ -636,10 +779,12 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     constexpr uint32_t CLS = (S >= 2) ? kPairTable : 0u;   // byte-class table
     constexpr uint32_t TAB = CLS + 256;                     // rows
     const uint32_t img = (a.img_bytes + 15) & ~15u;
-    uint32_t *s_ids = (uint32_t *)(smem + img);
+    uint8_t *s_mul = smem + img;                            // product table (product mode)
+    uint32_t *s_ids = (uint32_t *)(smem + img + a.mul_lds);
     uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
     copy16((uint4 *)smem, (const uint4 *)a.img, img / 16, (blockIdx.x * 613u) % (img / 16));
+    if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
     __syncthreads();
 
     const uint32_t one = a.one_off, wide = a.wide_mul;
@@ -770,6 +915,13 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
         }
     }
     const uint32_t rs = a.row_bytes;
+    if (a.mul_lds) {
+        uint32_t x = st[0] / rs;
+#pragma unroll
+        for (int k = 1; k < K; ++k) x = s_mul[x * a.n_sfa + st[k] / rs];
+        finish_ids(a, block_product(x, s_mul, a.n_sfa, s_scr), s_mul, s_scr, s_flag);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k] / rs;
     __syncthreads();   // the walk is over: the image region may be reused
@@ -793,11 +945,13 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
     const uint32_t rb = a.row_bytes, H = a.hot_rows;
     const uint32_t hot_bytes = ((H * rb) + 15) & ~15u;
     uint8_t *s_hot = smem + 512;
-    uint32_t *s_ids = (uint32_t *)(smem + 512 + hot_bytes);
+    uint8_t *s_mul = s_hot + hot_bytes;                     // product table (product mode)
+    uint32_t *s_ids = (uint32_t *)(s_mul + a.mul_lds);
     uint32_t *s_flag = s_ids + K * kBlock;
     uint32_t *s_scr = s_flag + 4;
     for (uint32_t i = threadIdx.x; i < 256; i += kBlock) s_cls[i] = a.cls[i];
     copy16((uint4 *)s_hot, (const uint4 *)a.img, hot_bytes / 16);
+    if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
     __syncthreads();
     const uint8_t *__restrict__ tab = a.img;
     auto step = [&](uint32_t s, uint32_t b) -> uint32_t {
@@ -862,6 +1016,13 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
                 pos[k] += act ? 1 : 0;
             }
         }
+    }
+    if (a.mul_lds) {
+        uint32_t x = st[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) x = s_mul[x * a.n_sfa + st[k]];
+        finish_ids(a, block_product(x, s_mul, a.n_sfa, s_scr), s_mul, s_scr, s_flag);
+        return;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k];
@@ -995,8 +1156,19 @@ uint32_t stage_bytes(const sfa_table *t, const Plan &P, bool speculative) {
 // mappings do not fit reads them from global memory instead.  The control
 // words sit in a fixed area at the start of every workspace that no other
 // write touches, so workspaces are shared by calls with different plans.
-void plan_grid(Plan &P, uint32_t n_dfa) {
+void plan_grid(Plan &P, uint32_t n_dfa, bool ids) {
     const uint32_t B = P.blocks;
+    if (ids) {
+        // product mode: one u32 id per block, runs of up to kIdRun blocks
+        P.map_stride = 0;
+        P.super_blocks = std::max(kIdRun, (B + kMaxRuns - 1) / kMaxRuns);
+        if (B <= P.super_blocks) P.super_blocks = B;
+        P.n_super = (B + P.super_blocks - 1) / P.super_blocks;
+        P.ws_maps = kWsHeader;
+        P.ws_groups = P.ws_maps + align256((uint64_t)B * 4);
+        P.ws_bytes = P.ws_groups + (P.n_super > 1 ? (size_t)P.n_super * 4 : 0);
+        return;
+    }
     P.map_stride = (n_dfa + 7) & ~7u;
     const uint32_t fit = P.stage_bytes / (P.map_stride * 2);   // mappings that fit in the staging LDS
     const uint32_t run = std::max(fit, 1u);
@@ -1083,7 +1255,7 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         P.groups = pick_groups(P.K * TB, t->L.n_dfa);
     }
     P.stage_bytes = stage_bytes(t, P, speculative);
-    plan_grid(P, t->L.n_dfa);
+    plan_grid(P, t->L.n_dfa, !speculative && t->L.mul_bytes);
     return SFA_OK;
 }
 
@@ -1153,13 +1325,15 @@ MatchArgs base_args(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d
     a.counter = (uint32_t *)d_ws;
     a.block_maps = (uint16_t *)((uint8_t *)d_ws + P.ws_maps);
     a.group_maps = (uint16_t *)((uint8_t *)d_ws + P.ws_groups);
+    a.block_ids = (uint32_t *)((uint8_t *)d_ws + P.ws_maps);
+    a.run_ids = (uint32_t *)((uint8_t *)d_ws + P.ws_groups);
     a.out = d_out;
     return a;
 }
 
 size_t scratch_lds(const Plan &P, uint32_t n_dfa) {
     const uint32_t G = std::max({P.groups, P.final_groups, P.n_super > 1 ? P.groups1 : 1u});
-    return G > 1 ? (size_t)G * n_dfa * 4 : 0;
+    return std::max<size_t>(G > 1 ? (size_t)G * n_dfa * 4 : 0, 64);   // >= one word per wave
 }
 
 }  // namespace
@@ -1196,6 +1370,11 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
     MatchArgs a = base_args(t, d_in, n, d_ws, d_out, P);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
+    if (t->L.mul_bytes) {
+        a.mul = t->d_base + t->L.off_mul;
+        a.mul_lds = (t->L.mul_bytes + 15) & ~15u;
+        a.n_sfa = t->L.n_sfa;
+    }
     if (P.S) {
         const Image &im = t->L.img[stride_index(P.S)];
         a.img = t->d_base + im.off;
@@ -1205,7 +1384,7 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.wide_mul = t->L.C * t->L.C;
         a.region_bytes = (im.bytes + 15) & ~15u;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        const size_t lds = a.region_bytes + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        const size_t lds = a.region_bytes + a.mul_lds + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         switch (P.S) {
             case 4: e = dispatch_shape<4>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a); break;
@@ -1220,7 +1399,7 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         const uint32_t hot_bytes = ((a.hot_rows * a.row_bytes) + 15) & ~15u;
         a.region_bytes = 512 + hot_bytes;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        const size_t lds = a.region_bytes + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        const size_t lds = a.region_bytes + a.mul_lds + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.blocks, lds, s, a);
         else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.blocks, lds, s, a);

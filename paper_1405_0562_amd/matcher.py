@@ -91,12 +91,12 @@ class Table:
     """A compiled automaton resident in device memory (HBM)."""
 
     def __init__(self, compiled: Compiled, device=None, force_global: bool = False, lds_budget: int = 0,
-                 renumber: int = 0, profile_sample: np.ndarray | None = None, stream=None):
+                 renumber: int = 0, profile_sample: np.ndarray | None = None, product: bool = True, stream=None):
         self.compiled = compiled
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         desc = compiled.desc()
         sample = None if profile_sample is None else np.ascontiguousarray(profile_sample, dtype=np.uint8)
-        opts = _capi.LoadOptions(int(force_global), int(lds_budget), int(renumber), 0,
+        opts = _capi.LoadOptions(int(force_global), int(lds_budget), int(renumber), int(not product),
                                  ctypes.c_void_p(sample.ctypes.data) if sample is not None else None,
                                  0 if sample is None else sample.size)
         nbytes = ctypes.c_size_t()

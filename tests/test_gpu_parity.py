@@ -265,3 +265,73 @@ def test_workspace_shared_by_one_and_two_level_plans():
     for n_chunks, spec in [(65536, False), (65536, True), (1 << 20, False), (4096, True), (7, False),
                            (1 << 22, False), (65536, True), (0, False), (1 << 20, True)]:
         assert run(W.REGEX_C2, data, n_chunks=n_chunks, speculative=spec, x=x) == want, (n_chunks, spec)
+
+
+# --------------------------------------------------------------------------
+# composition through the product table vs through the mappings; every
+# launch plan of the walk kernels
+# --------------------------------------------------------------------------
+PRODUCT_RX = [W.REGEX_C1, W.REGEX_C2, "(ab)*", W.rn_regex(3), ".*abc.*", "(a|b)*a(a|b){2}", ".*"]
+
+
+def small_text(rx, seed, n):
+    if rx == W.REGEX_C1:
+        return W.c1_input(seed, n=n - n % 2)
+    if rx == W.rn_regex(3):
+        rng = np.random.default_rng(seed)
+        return rng.choice(np.frombuffer(b"0123456789", np.uint8), size=n)
+    return W.uniform_over(W.rng_for(seed, 3), np.frombuffer(b"abc", np.uint8), n)
+
+
+@pytest.mark.parametrize("rx", PRODUCT_RX)
+def test_product_and_mapping_composition_agree(rx):
+    data = small_text(rx, 31, (1 << 20) + 333)
+    want = oracle_result(rx, data)
+    c = sfa.compile(rx)
+    tp = sfa.load(c)
+    tm = sfa.load(c, product=False)
+    tg = sfa.load(c, force_global=True)
+    assert tp.info["product_table"] == int(c.info.n_sfa <= 128)
+    assert tm.info["product_table"] == 0
+    assert tg.info["product_table"] == tp.info["product_table"]
+    x = to_device(data)
+    for n_chunks in (0, 1, 3, 777, 65536, 1 << 20, 1 << 22):
+        for t in (tp, tm, tg):
+            say(rx[:30], "chunks", n_chunks, "product", t.info["product_table"], "lds", t.info["table_in_lds"])
+            assert sfa.match(t, x, n_chunks=n_chunks).tolist() == want, (n_chunks, t.info)
+
+
+LDS_SHAPES = [(1, 64, 2, 256), (1, 128, 2, 256), (1, 128, 4, 256), (2, 64, 2, 256), (2, 64, 4, 256),
+              (2, 128, 2, 256), (4, 64, 2, 256), (8, 32, 2, 256),
+              (1, 64, 2, 512), (1, 128, 2, 512), (2, 64, 2, 512), (2, 128, 2, 512), (4, 32, 2, 512), (4, 64, 2, 512),
+              (1, 32, 2, 1024), (1, 64, 2, 1024), (1, 128, 2, 1024), (2, 32, 2, 1024), (2, 64, 2, 1024)]
+
+
+@pytest.mark.parametrize("product", [True, False])
+@pytest.mark.parametrize("rx", [W.REGEX_C1, W.REGEX_C2])
+def test_every_lds_launch_plan(rx, product):
+    data = small_text(rx, 41, (2 << 20) + 4099)
+    want = oracle_result(rx, data)
+    t = sfa.load(sfa.compile(rx), product=product)
+    assert t.info["strides"] == 2 | 4 | 16
+    x = to_device(data)
+    for stride in (1, 2, 4):
+        for (k, g, d, tb) in LDS_SHAPES:
+            for lpc in (1, 4):
+                for n_chunks in (1000, 65536):
+                    plan = dict(stride=stride, pieces=k, load_bytes=g, depth=d, block_threads=tb,
+                                lanes_per_chunk=lpc)
+                    got = sfa.match(t, x, n_chunks=n_chunks, plan=plan).tolist()
+                    assert got == want, (plan, n_chunks)
+
+
+@pytest.mark.parametrize("product", [True, False])
+def test_every_global_launch_plan(product):
+    rx = W.REGEX_C2
+    data = small_text(rx, 43, (2 << 20) + 17)
+    want = oracle_result(rx, data)
+    t = sfa.load(sfa.compile(rx), force_global=True, product=product)
+    x = to_device(data)
+    for k in (1, 2, 4, 8):
+        for n_chunks in (0, 1000, 65536):
+            assert sfa.match(t, x, n_chunks=n_chunks, plan=dict(pieces=k)).tolist() == want, (k, n_chunks)

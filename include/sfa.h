@@ -274,7 +274,10 @@ sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64
  *   sfa_batch_workspace_bytes / sfa_batch_upload
  *                      the caller provides a device workspace (256-byte
  *                      aligned) and uploads the plan's descriptors into it once
- *                      (async on stream).
+ *                      (async on stream), together with a contiguous copy of
+ *                      the tables' stride-1 walk images when they are staged
+ *                      in LDS (taken from the tables' packed host images when
+ *                      the batch is created).
  *   sfa_match_batch    launches the walk, group and composition kernels only
  *                      (no allocation, no host synchronisation, no memset),
  *                      so a stream capture of it can be replayed as a graph as

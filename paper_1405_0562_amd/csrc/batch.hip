@@ -25,6 +25,7 @@
 #include <string>
 #include <vector>
 
+#include "device.h"
 #include "internal.h"
 
 namespace {
@@ -73,6 +74,7 @@ struct BatchArgs {
     uint32_t piece, group;
     uint32_t lds_tables;     // 1: table images staged in LDS at lds_off
     uint32_t lds_bytes;
+    const uint8_t *lds_image;  // lds_tables: all staged images, contiguous (lds_bytes, multiple of 16)
 };
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
@@ -86,7 +88,8 @@ struct sfa_batch {
     uint64_t n_units = 0, n_items = 0;
     int device = 0;
     // workspace layout
-    uint64_t off_tables = 0, off_docs = 0, off_jobs = 0, off_gjobs = 0, off_units = 0, off_gmaps = 0, total = 0;
+    uint64_t off_tables = 0, off_docs = 0, off_jobs = 0, off_gjobs = 0, off_lds = 0, off_units = 0, off_gmaps = 0,
+             total = 0;
     std::vector<uint8_t> blob;   // bytes [off_tables, off_units) of the workspace
 };
 
@@ -111,12 +114,7 @@ template <int K, bool LDS>
 __global__ __launch_bounds__(kTB) void k_batch_walk(BatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     if constexpr (LDS) {
-        for (uint32_t t = 0; t < a.n_tables; ++t) {
-            const uint4 *src = (const uint4 *)a.tables[t].img;
-            uint4 *dst = (uint4 *)(smem + a.tables[t].lds_off);
-            const uint32_t n16 = (a.tables[t].img_bytes + 15) / 16;
-            for (uint32_t i = threadIdx.x; i < n16; i += kTB) dst[i] = src[i];
-        }
+        sfa_dev::copy16((uint4 *)smem, (const uint4 *)a.lds_image, a.lds_bytes / 16);
         __syncthreads();
     }
     uint64_t pos[K], end[K], unit[K];
@@ -392,6 +390,8 @@ extern "C" sfa_status sfa_batch_create(const sfa_table *const *tables, uint32_t 
         off = align256(off + sizeof(BJob) * std::max<size_t>(1, bj.size()));
         b->off_gjobs = off;
         off = align256(off + sizeof(BGroupJob) * std::max<size_t>(1, gj.size()));
+        b->off_lds = off;
+        off = align256(off + b->lds_bytes);
         b->off_units = off;
         off = align256(off + 4 * std::max<uint64_t>(1, units));
         b->off_gmaps = off;
@@ -405,6 +405,11 @@ extern "C" sfa_status sfa_batch_create(const sfa_table *const *tables, uint32_t 
         put(b->off_docs, docs.data(), sizeof(BDoc) * docs.size());
         put(b->off_jobs, bj.data(), sizeof(BJob) * bj.size());
         put(b->off_gjobs, gj.data(), sizeof(BGroupJob) * gj.size());
+        if (b->lds_tables)   // the LDS images of all tables, contiguous, from the tables' packed host images
+            for (uint32_t t = 0; t < n_tables; ++t) {
+                const Image &im = tables[t]->L.img[0];
+                put(b->off_lds + bt[t].lds_off, tables[t]->image.data() + im.off, im.bytes);
+            }
     } catch (const std::bad_alloc &) {
         delete b;
         return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
@@ -487,6 +492,7 @@ extern "C" sfa_status sfa_match_batch(const sfa_batch *b, const uint8_t *d_data,
     a.group = b->group;
     a.lds_tables = b->lds_tables;
     a.lds_bytes = b->lds_bytes;
+    a.lds_image = ws + b->off_lds;
     hipStream_t s = (hipStream_t)stream;
     const uint64_t lanes = (b->n_units + b->K - 1) / b->K;
     const uint64_t wblocks = (lanes + kTB - 1) / kTB;

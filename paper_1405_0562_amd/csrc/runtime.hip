@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "device.h"
 #include "internal.h"
 
 // ---------------------------------------------------------------------------
@@ -68,6 +69,15 @@ constexpr uint64_t kWsHeader = 4096;         // workspace control words: [0] top
 constexpr uint32_t kMaxRuns = kWsHeader / 4 - 1;
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Byte-pair class table layout.  Entry h = b0 | b1 << 8 (b0 first in the
+// text) sits at h with its bits 2..7 XORed with bits 0..5 of b1: the LDS
+// bank of an entry then depends on both bytes, not on b0 alone (text over a
+// small alphabet would otherwise put every lookup of a wave in a few banks).
+// A permutation within each 256-entry block, so the table stays 64 KiB.
+__host__ __device__ inline uint32_t pair_slot(uint32_t h) { return h ^ ((h >> 6) & 0xfcu); }
+// Both pair slots of a 4-byte word at once: low half and high half of the result.
+__host__ __device__ inline uint32_t pair_slots(uint32_t w) { return w ^ ((w >> 6) & 0x00fc00fcu); }
 
 }  // namespace
 
@@ -330,7 +340,7 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
         uint64_t o = im.off;
         if (S >= 2) {
             for (uint32_t h = 0; h < kPairTable; ++h)   // little endian: low byte comes first in the text
-                img[o + h] = (uint8_t)(2 * (d->byte_class[h & 255] * C + d->byte_class[h >> 8]));
+                img[o + pair_slot(h)] = (uint8_t)(2 * (d->byte_class[h & 255] * C + d->byte_class[h >> 8]));
             o += kPairTable;
         }
         for (int b = 0; b < 256; ++b) img[o + b] = (uint8_t)(2 * d->byte_class[b]);
@@ -432,6 +442,8 @@ extern "C" sfa_status sfa_free_table(sfa_table *t) {
 // ---------------------------------------------------------------------------
 namespace {
 
+using sfa_dev::copy16;
+
 struct MatchArgs {
     const uint8_t *in;
     uint64_t n;
@@ -470,29 +482,6 @@ struct MatchArgs {
     uint32_t *run_ids;       // product mode: [n_super] run products
     sfa_result *out;
 };
-
-// Copies n16 16-byte words from global memory to LDS; each thread has U
-// loads in flight before it waits, so the copy costs one memory latency per
-// U * blockDim.x words instead of one per word.  Indices past the end are
-// clamped to the last word (a repeated copy of the same value), which keeps
-// the loads unconditional and the staging array in registers.  The copy
-// starts at word `rot` (mod n16), so blocks that stage the same table at the
-// same time spread their requests over different memory channels.
-template <int U = 8>
-__device__ __forceinline__ void copy16(uint4 *dst, const uint4 *__restrict__ src, uint32_t n16, uint32_t rot = 0) {
-    for (uint32_t base = threadIdx.x; base < n16; base += U * blockDim.x) {
-        uint4 r[U];
-        uint32_t j[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t i = min(base + u * blockDim.x, n16 - 1) + rot;
-            j[u] = i >= n16 ? i - n16 : i;
-            r[u] = src[j[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) dst[j[u]] = r[u];
-    }
-}
 
 // Phase 1 of a composition: the elements 0..E-1 (mappings, in text order) are
 // cut into G groups of R consecutive elements; for every (group g, start
@@ -851,7 +840,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
                             uint32_t p0[K], p1[K];
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
-                                const uint32_t w = word_of(cur[k][v], d);
+                                const uint32_t w = pair_slots(word_of(cur[k][v], d));
                                 p0[k] = smem[w & 0xffffu];
                                 p1[k] = smem[w >> 16];
                             }
@@ -863,7 +852,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
                             uint32_t p0[K], p1[K];
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
-                                const uint32_t w = word_of(cur[k][v], d);
+                                const uint32_t w = pair_slots(word_of(cur[k][v], d));
                                 p0[k] = smem[w & 0xffffu];
                                 p1[k] = smem[w >> 16];
                             }

@@ -111,6 +111,7 @@ class Table:
         check(lib().sfa_table_get_info(self._h, ctypes.byref(ti)))
         self.info = {f: getattr(ti, f) for f, _ in _capi.TableInfo._fields_}
         self._ws = {}
+        self._calls = {}   # (entry point, n, n_chunks, stream, plan) -> prepared call
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -146,6 +147,15 @@ def load(compiled: Compiled, **kw) -> Table:
     return Table(compiled, **kw)
 
 
+def _prepare(fn_name: str, table: Table, n: int, n_chunks: int, stream, sp: int, plan: dict | None):
+    """Entry point and the arguments that do not change between calls of one shape."""
+    ws = table.workspace(n, n_chunks, stream)
+    if plan is None:
+        return getattr(lib(), fn_name), (), ws
+    p = _capi.Plan(*(int(plan.get(f, 0)) for f, _ in _capi.Plan._fields_))
+    return lib().sfa_match_ex, (ctypes.byref(p), p), ws
+
+
 def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: torch.Tensor | None, stream,
            plan: dict | None = None):
     if data.dtype != torch.uint8 or not data.is_cuda or data.dim() != 1 or not data.is_contiguous():
@@ -153,16 +163,21 @@ def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: t
     if data.device != table.device:
         raise ValueError("data and table are on different devices")
     n = data.numel()
-    ws = table.workspace(n, n_chunks, stream)
+    sp = _stream_ptr(stream)
+    key = (fn_name, n, n_chunks, sp, None if plan is None else tuple(sorted(plan.items())))
+    call = table._calls.get(key)
+    if call is None:
+        call = table._calls[key] = _prepare(fn_name, table, n, n_chunks, stream, sp, plan)
+    fn, extra, ws = call
     if out is None:
         out = torch.empty(2, dtype=torch.int32, device=table.device)
-    args = [table.handle, ctypes.c_void_p(data.data_ptr() if n else 0), n, n_chunks]
-    if plan is not None:
-        fn_name = "sfa_match_ex"
-        args.append(ctypes.byref(_capi.Plan(*(int(plan.get(f, 0)) for f, _ in _capi.Plan._fields_))))
-    args += [ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
-             ctypes.c_void_p(_stream_ptr(stream))]
-    check(getattr(lib(), fn_name)(*args))
+    if extra:
+        st = fn(table.handle, data.data_ptr() if n else None, n, n_chunks, extra[0], ws.data_ptr(), ws.numel(),
+                out.data_ptr(), sp or None)
+    else:
+        st = fn(table.handle, data.data_ptr() if n else None, n, n_chunks, ws.data_ptr(), ws.numel(),
+                out.data_ptr(), sp or None)
+    check(st)
     return out
 
 

@@ -811,13 +811,20 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
             // before step j is walked
             constexpr int V = G / 16;
             uint4 buf[D][K][V];
+            // With a 2-deep ring the compiler would spread a step's loads over
+            // the walk of the previous step; the 16-byte loads that share a
+            // 128-byte line then reach the L2 microseconds apart and the line
+            // is fetched again after an eviction (measured: 1.19x the input
+            // bytes).  Scheduling barriers keep them together.
             auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
+                if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const uint64_t base = (step < nb[k]) ? pos[k] + (uint64_t)G * step : pos[0];
 #pragma unroll
                     for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
                 }
+                if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
             };
             auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
                 uint32_t t[K];
@@ -1094,7 +1101,7 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
 // shapes of the LDS walk.  K * G * D bounds the load buffers in registers.
 #define SFA_LDS_SHAPES(X) \
     X(1, 64, 2, 256) X(1, 128, 2, 256) X(1, 128, 4, 256) X(2, 64, 2, 256) X(2, 64, 4, 256) \
-    X(2, 128, 2, 256) X(4, 64, 2, 256) X(8, 32, 2, 256) \
+    X(2, 128, 2, 256) X(2, 128, 3, 256) X(2, 128, 4, 256) X(3, 128, 3, 256) X(4, 64, 2, 256) X(8, 32, 2, 256) \
     X(1, 64, 2, 512) X(1, 128, 2, 512) X(2, 64, 2, 512) X(2, 128, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
     X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
 
@@ -1196,7 +1203,10 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         uint32_t S = 0;
         for (uint32_t s : {4u, 2u, 1u})
             if (!S && t->L.img[stride_index(s)].present) S = s;
-        uint32_t K = 2, G = 128, D = 2, TB = 256, LPC = 1;
+        // default: 2 pieces per lane, 128-byte steps, loads issued 3 steps
+        // ahead (the deepest ring that stays in registers; it hides HBM
+        // latency with one wave per SIMD)
+        uint32_t K = 2, G = 128, D = 4, TB = 256, LPC = 1;
         if (user) {
             if (user->stride) {
                 const int si = stride_index(user->stride);

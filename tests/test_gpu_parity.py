@@ -302,7 +302,7 @@ def test_product_and_mapping_composition_agree(rx):
 
 
 LDS_SHAPES = [(1, 64, 2, 256), (1, 128, 2, 256), (1, 128, 4, 256), (2, 64, 2, 256), (2, 64, 4, 256),
-              (2, 128, 2, 256), (4, 64, 2, 256), (8, 32, 2, 256),
+              (2, 128, 2, 256), (2, 128, 3, 256), (2, 128, 4, 256), (3, 128, 3, 256), (4, 64, 2, 256), (8, 32, 2, 256),
               (1, 64, 2, 512), (1, 128, 2, 512), (2, 64, 2, 512), (2, 128, 2, 512), (4, 32, 2, 512), (4, 64, 2, 512),
               (1, 32, 2, 1024), (1, 64, 2, 1024), (1, 128, 2, 1024), (2, 32, 2, 1024), (2, 64, 2, 1024)]
 

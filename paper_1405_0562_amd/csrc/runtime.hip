@@ -772,6 +772,44 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     uint32_t *s_ids = (uint32_t *)(smem + img + a.mul_lds);
     uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
+    uint64_t c0, c1, pos[K], end[K];
+    lane_pieces<K, G, TB>(a, c0, c1, pos, end);
+    // head: single bytes up to 16-byte alignment (the same for all pieces);
+    // body[k]: where piece k's 16-byte aligned G-byte groups start
+    const uint32_t head = c1 > c0 ? (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15) : 0u;
+    uint64_t body[K], nb[K], maxnb = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        body[k] = min(end[k], pos[k] + head);
+        nb[k] = (end[k] - body[k]) / G;
+        maxnb = max(maxnb, nb[k]);
+    }
+    // ring of D load buffers: the loads of step j + D - 1 are issued before
+    // step j is walked.  Piece 0 is the longest, so a piece past its last
+    // group re-reads piece 0's first group (discarded).
+    constexpr int V = G / 16;
+    uint4 buf[D][K][V];
+    // With a 2-deep ring the compiler would spread a step's loads over the
+    // walk of the previous step; the 16-byte loads that share a 128-byte line
+    // then reach the L2 microseconds apart and the line is fetched again
+    // after an eviction (measured: 1.19x the input bytes).  Scheduling
+    // barriers keep them together.
+    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
+        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t base = (step < nb[k]) ? body[k] + (uint64_t)G * step : body[0];
+#pragma unroll
+            for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
+        }
+        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
+    };
+    // the first loads go out before the table is staged, so their latency
+    // overlaps the staging
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d)
+        if ((uint64_t)d < maxnb) issue(buf[d], d);
+
     copy16((uint4 *)smem, (const uint4 *)a.img, img / 16, (blockIdx.x * 613u) % (img / 16));
     if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
     __syncthreads();
@@ -781,15 +819,11 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     // one byte: f <- delta_s[f, class(b)]
     auto step1 = [&](uint32_t st, uint32_t b) -> uint32_t { return row(st + one + smem[CLS + b]); };
 
-    uint64_t c0, c1, pos[K], end[K];
-    lane_pieces<K, G, TB>(a, c0, c1, pos, end);
     uint32_t st[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = 0;     // f_I
 
     if (c1 > c0) {
-        // head: single bytes up to 16-byte alignment (the same for all pieces)
-        const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15);
         for (uint32_t i = 0; i < head; ++i) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -799,33 +833,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
                 pos[k] += act ? 1 : 0;
             }
         }
-        // body: G-byte groups (16-byte aligned loads), next group loaded first
-        uint64_t nb[K], maxnb = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            nb[k] = (end[k] - pos[k]) / G;
-            maxnb = max(maxnb, nb[k]);
-        }
         if (maxnb) {
-            // ring of D load buffers: the loads of step j + D - 1 are issued
-            // before step j is walked
-            constexpr int V = G / 16;
-            uint4 buf[D][K][V];
-            // With a 2-deep ring the compiler would spread a step's loads over
-            // the walk of the previous step; the 16-byte loads that share a
-            // 128-byte line then reach the L2 microseconds apart and the line
-            // is fetched again after an eviction (measured: 1.19x the input
-            // bytes).  Scheduling barriers keep them together.
-            auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
-                if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const uint64_t base = (step < nb[k]) ? pos[k] + (uint64_t)G * step : pos[0];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
-                }
-                if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
-            };
             auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
                 uint32_t t[K];
 #pragma unroll
@@ -871,9 +879,6 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) st[k] = (step < nb[k]) ? t[k] : st[k];
             };
-#pragma unroll
-            for (int d = 0; d < D - 1; ++d)
-                if ((uint64_t)d < maxnb) issue(buf[d], d);
             uint64_t j = 0;
             // steady state: every issued step exists, no bounds checks
             for (; j + 2 * D - 1 <= maxnb; j += D) {

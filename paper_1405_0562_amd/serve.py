@@ -209,7 +209,8 @@ class GpuBackend:
     """Device side of the server: pinned staging, device pool, batch and single launches."""
 
     def __init__(self, tables, pool_bytes: int = 1 << 30, n_streams: int = 3, piece_bytes: int = 4096,
-                 units_per_lane: int = 2, device=None, max_batch_requests: int = 4096, result_slots: int = 64):
+                 units_per_lane: int = 2, device=None, max_batch_requests: int = 4096, result_slots: int = 64,
+                 warmup: bool = True):
         import torch
         from .batch import Batch, BatchOptions
         self.torch = torch
@@ -226,6 +227,23 @@ class GpuBackend:
         self.result_slots = [torch.empty((max_batch_requests, 2), dtype=torch.int32, pin_memory=True)
                              for _ in range(result_slots)]
         self.next_slot = 0
+        if warmup:
+            self.warmup()
+
+    def warmup(self) -> None:
+        """Run the launch paths once on every stream before serving: a small
+        and a 1 MiB single-stream match (different kernel shapes) and a
+        two-request batch.  First launches load kernel code and set up
+        streams, which would otherwise land on the first requests served."""
+        small = np.zeros(4096, dtype=np.uint8)
+        big = np.zeros(1 << 20, dtype=np.uint8)
+        for _ in self.streams:
+            handles = [self.launch_single(Request(-1, 0, small, 0.0), 0),
+                       self.launch_single(Request(-1, 0, big, 0.0), 1 << 16),
+                       self.launch_batch([Request(-1, 0, small, 0.0), Request(-1, len(self.tables) - 1, small, 0.0)],
+                                         (1 << 16) + (1 << 20))]
+            for h in handles:
+                h[0].synchronize()
 
     def _stream(self):
         s = self.streams[self.next_stream % len(self.streams)]

@@ -69,6 +69,119 @@ def cpu_baseline(rx, data, budget_s: float):
     }, [full_q, int(d.accept[full_q])]
 
 
+def cpu_baseline_sizes(rx, inputs, budget_s: float = 0.2):
+    """The oracle (Algorithm 2 in C, one core) timed per input of the
+    crossover study: seconds per pass and its result for each input."""
+    from oracle.automata import compile_regex
+    from oracle import scan
+    d = compile_regex(rx)
+    tab = scan.table_u32(d)
+    out = []
+    for data in inputs:
+        q = scan.scan(d, data, table=tab)
+        reps, elapsed = 0, 0.0
+        while elapsed < budget_s or reps < 3:
+            t0 = time.perf_counter()
+            scan.scan(d, data, table=tab)
+            elapsed += time.perf_counter() - t0
+            reps += 1
+        out.append((elapsed / reps, [q, int(d.accept[q])]))
+    return out
+
+
+def crossover_study(seed: int):
+    """Small inputs: one sfa_match call end to end (launch to result on the
+    host) with the input already in device memory, and with a copy from
+    pinned host memory first, against one pass of the oracle's sequential
+    DFA on one host core.  The regex is the overhead experiment's shape."""
+    import numpy as np
+    import torch
+    import paper_1405_0562_amd as sfa
+    import workloads as W
+    rx = W.REGEX_C1
+    sizes = [1 << k for k in range(10, 25, 2)]
+    inputs = [W.c1_input(seed, n=(s // 10) * 10) for s in sizes]
+    table = sfa.load(sfa.compile(rx))
+    out = torch.empty(2, dtype=torch.int32, device="cuda")
+    rows = []
+    cpu = cpu_baseline_sizes(rx, inputs)
+    for data, (cpu_s, want) in zip(inputs, cpu):
+        pinned = torch.from_numpy(data).pin_memory()
+        dev = pinned.cuda()
+        for _ in range(3):
+            sfa.match(table, dev, out=out).tolist()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            got = sfa.match(table, dev, out=out).tolist()
+        resident_s = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dev.copy_(pinned, non_blocking=True)
+            got2 = sfa.match(table, dev, out=out).tolist()
+        h2d_s = (time.perf_counter() - t0) / reps
+        rows.append({"bytes": int(data.size), "gpu_resident_us": resident_s * 1e6, "gpu_with_h2d_us": h2d_s * 1e6,
+                     "cpu_oracle_us": cpu_s * 1e6, "parity": got == want and got2 == want})
+    cross = lambda key: next((r["bytes"] for r in rows if r[key] < r["cpu_oracle_us"]), None)
+    return {"regex": rx, "rows": rows,
+            "crossover_bytes_resident": cross("gpu_resident_us"),
+            "crossover_bytes_with_h2d": cross("gpu_with_h2d_us")}
+
+
+def rn_study(seed: int, size: int):
+    """Scalability regexes r_n (Section 6.2) on ~1 GiB accepted texts, and
+    r_n | a* on all-'a' text: host construction time, where the D-SFA is
+    placed (LDS image, global table with hot rows, or over the state cap and
+    matched by the speculative kernel), GPU throughput, and the oracle's
+    sequential DFA on one core over the same bytes (also the parity check)."""
+    import numpy as np
+    import torch
+    import paper_1405_0562_amd as sfa
+    import workloads as W
+    big = 1_100_000   # state cap that admits the D-SFAs of r500 and r_a (about 10^6 states)
+    cases = [("r5", W.rn_regex(5), 5, None), ("r50", W.rn_regex(50), 50, None),
+             ("r500, default cap", W.rn_regex(500), 500, None), ("r500", W.rn_regex(500), 500, big),
+             ("r_a", W.ra_regex(500), None, big)]
+    rows = []
+    out = torch.empty(2, dtype=torch.int32, device="cuda")
+    for name, rx, n, cap in cases:
+        print("[rn study] %s: building input and automata" % name, file=sys.stderr, flush=True)
+        data = W.rn_input(seed, n, size) if n else np.full(size, ord("a"), dtype=np.uint8)
+        t0 = time.perf_counter()
+        comp = sfa.compile(rx) if cap is None else sfa.compile(rx, sfa_cap=cap)
+        compile_s = time.perf_counter() - t0
+        table = sfa.load(comp)
+        x = torch.from_numpy(data).cuda()
+        use_sfa = comp.info.n_sfa > 0
+        fn = sfa.match if use_sfa else sfa.match_speculative
+        fn(table, x, out=out)
+        torch.cuda.synchronize()
+        reps = 3
+        s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_ev.record()
+        for _ in range(reps):
+            fn(table, x, out=out)
+        e_ev.record()
+        torch.cuda.synchronize()
+        ms = s_ev.elapsed_time(e_ev) / reps
+        got = out.tolist()
+        del x
+        print("[rn study] %s: GPU %.3f ms; timing the oracle" % (name, ms), file=sys.stderr, flush=True)
+        (cpu_s, want), = cpu_baseline_sizes(rx, [data], budget_s=0.0)
+        info = table.info
+        comp_info = (comp.info.n_dfa, comp.info.n_sfa)
+        placement = ("speculative (D-SFA over the state cap)" if not use_sfa else
+                     "LDS image, strides %s" % [s for s, bit in ((1, 2), (2, 4), (4, 16)) if info["strides"] & bit]
+                     if info["table_in_lds"] else "global table, %d hot rows in LDS" % info["hot_rows"])
+        del table, comp
+        rows.append({"regex": name, "n_dfa": comp_info[0], "n_sfa": comp_info[1],
+                     "compile_s": compile_s, "placement": placement, "product_table": info["product_table"],
+                     "bytes": int(data.size), "gpu_gbs": data.size / (ms * 1e-3) / 1e9, "gpu_ms": ms,
+                     "cpu_oracle_gbs": data.size / cpu_s / 1e9, "result": got, "oracle_result": want,
+                     "parity": got == want})
+    return {"rows": rows}
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha1()
@@ -222,6 +335,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of the workload size (counter calibration)")
+    ap.add_argument("--study", choices=["crossover", "rn"], default=None,
+                    help="run a study instead of the benchmark and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -232,6 +347,12 @@ def main():
     import torch
     import paper_1405_0562_amd as sfa
 
+    if args.study == "crossover":
+        print(json.dumps({"study": "small-input crossover", **crossover_study(args.seed)}), flush=True)
+        return
+    if args.study == "rn":
+        print(json.dumps({"study": "r_n scalability and placement", **rn_study(args.seed, 1 << 30)}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     if args.calibrate_copy:
         dev = torch.device("cuda", 0)

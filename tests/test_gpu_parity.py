@@ -335,3 +335,20 @@ def test_every_global_launch_plan(product):
     for k in (1, 2, 4, 8):
         for n_chunks in (0, 1000, 65536):
             assert sfa.match(t, x, n_chunks=n_chunks, plan=dict(pieces=k)).tolist() == want, (k, n_chunks)
+
+
+def test_dsfa_over_65536_states_uses_32_bit_ids():
+    # r_128 has 4*128^2 + 2*128 = 65,792 D-SFA states: 32-bit walk-table
+    # entries, read by the global-table walk with hot rows in LDS
+    rx = W.rn_regex(128)
+    c = sfa.compile(rx, sfa_cap=70_000)
+    assert c.info.n_sfa == 65_792
+    t = sfa.load(c)
+    assert t.info["next_bytes"] == 4 and t.info["table_in_lds"] == 0 and t.info["hot_rows"] > 0
+    words = W.rn_input(5, 128, (4 << 20) + 256 * 7)
+    rng = np.random.default_rng(4)
+    noise = rng.choice(np.frombuffer(b"0123456789", np.uint8), size=(1 << 20) + 3)
+    for data in (words, noise, words[: (1 << 20) + 77]):
+        want = oracle_result(rx, data)
+        for n_chunks in (0, 1000, 65536):
+            assert run_table(t, rx, data, n_chunks) == want, n_chunks

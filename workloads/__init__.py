@@ -36,7 +36,7 @@ __all__ = [
     "REGEX_C1", "REGEX_C2", "C1_N", "C2_N", "C3_N",
     "rng_for", "c1_input", "c2_input", "c3_keywords", "c3_regex", "c3_input",
     "uniform_over", "ALPHABET_C4", "family_regex", "c4_regexes", "c4_doc_lengths",
-    "c4_docs", "c5_regexes", "c5_requests", "Request", "rn_regex", "ra_regex",
+    "c4_docs", "c5_regexes", "c5_requests", "Request", "rn_regex", "ra_regex", "rn_input",
 ]
 
 REGEX_C1 = "(([0-4][5-9]){5})*"
@@ -86,6 +86,21 @@ def uniform_over(rng: np.random.Generator, alphabet: bytes, n: int,
         hi = min(n, lo + block)
         idx = rng.integers(0, k, size=hi - lo, dtype=np.uint8)
         out[lo:hi] = alpha[idx]
+    return out
+
+
+def rn_input(seed: int, n: int, size: int) -> np.ndarray:
+    """A word of r_n: ``size // (2n)`` blocks of n uniform digits from 0-4
+    followed by n uniform digits from 5-9 (the accepted texts of the
+    scalability experiment, Section 6.2)."""
+    blocks = size // (2 * n)
+    rng = rng_for(seed, 11)
+    out = np.empty(blocks * 2 * n, dtype=np.uint8)
+    view = out.reshape(blocks, 2, n)
+    step = max(1, (1 << 26) // (2 * n))
+    for lo in range(0, blocks, step):
+        hi = min(blocks, lo + step)
+        view[lo:hi] = rng.integers(0, 5, size=(hi - lo, 2, n), dtype=np.uint8) + np.array([48, 53], np.uint8)[None, :, None]
     return out
 
 

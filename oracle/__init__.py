@@ -25,6 +25,10 @@ Modules
               the deterministic simplification), the reverse composition of
               Section 2.1, parallel SFA computation (Algorithm 5, Section 5.2)
               and speculative DFA simulation (Algorithm 3, Section 3).
+``nsfa``      the SFA built from an NFA: position automaton (Glushkov), the
+              NFA run from I, Algorithm 4 over correspondences Q -> P(Q),
+              composition of correspondences and Algorithm 5 with
+              S_fin = union of f_fin(q) over q in I.
 ``scan``      Algorithm 2 in plain C (``seqscan.c``) for large inputs.
 ``build``     compiles ``seqscan.c`` with gcc.
 

@@ -182,6 +182,66 @@ def rn_study(seed: int, size: int):
     return {"rows": rows}
 
 
+def cpu_baseline_nfa_sets(rx, inputs):
+    """The oracle's NFA run (position automaton, from I) over each input:
+    (final state set as a bit mask, accept) -- the N-SFA result's definition."""
+    from oracle import nsfa as onsfa
+    a = onsfa.glushkov(rx)
+    out = []
+    for data in inputs:
+        s = onsfa.nfa_run(a, bytes(data))
+        out.append((s, bool(s & a.final)))
+    return out
+
+
+def nsfa_study(seed: int, size: int):
+    """D-SFA (minimal DFA) against N-SFA (position automaton) matching of the
+    same regex on the same bytes: state counts, placement and throughput.
+    Accept bits are checked against the oracle's sequential DFA over all the
+    bytes, and the N-SFA's final NFA state set against the oracle's NFA run
+    on a 1 MiB prefix."""
+    import numpy as np
+    import torch
+    import paper_1405_0562_amd as sfa
+    import workloads as W
+    kw = W.c4_regexes(seed)[0]
+    text = W.uniform_over(W.rng_for(seed, 3), W.ALPHABET_C4, size)
+    cases = [(W.REGEX_C2, W.c2_input(seed, size)), (kw, text), (W.REGEX_C1, W.c1_input(seed, size - size % 10))]
+    rows = []
+    out = torch.empty(2, dtype=torch.int32, device="cuda")
+    for rx, data in cases:
+        print("[nsfa study] %s" % rx[:40], file=sys.stderr, flush=True)
+        x = torch.from_numpy(data).cuda()
+        prefix = torch.from_numpy(data[: 1 << 20].copy()).cuda()
+        (cpu_s, want), = cpu_baseline_sizes(rx, [data], budget_s=0.0)
+        (want_set, want_acc), = cpu_baseline_nfa_sets(rx, [data[: 1 << 20]])
+        row = {"regex": rx if len(rx) < 60 else rx[:57] + "...", "bytes": int(data.size)}
+        for kind in ("dsfa", "nsfa"):
+            comp = sfa.compile_nsfa(rx) if kind == "nsfa" else sfa.compile(rx)
+            table = sfa.load(comp)
+            sfa.match(table, x, out=out)
+            torch.cuda.synchronize()
+            s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_ev.record()
+            for _ in range(10):
+                sfa.match(table, x, out=out)
+            e_ev.record()
+            torch.cuda.synchronize()
+            ms = s_ev.elapsed_time(e_ev) / 10
+            q, acc = out.tolist()
+            entry = {"dfa_states": comp.info.n_dfa, "sfa_states": comp.info.n_sfa,
+                     "product_table": table.info["product_table"], "table_in_lds": table.info["table_in_lds"],
+                     "gbs": data.size / (ms * 1e-3) / 1e9, "accept": acc, "accept_parity": acc == want[1]}
+            if kind == "nsfa":
+                qp, accp = sfa.match(table, prefix).tolist()
+                entry["prefix_set_parity"] = (comp.nsfa_set(qp), bool(accp)) == (want_set, want_acc)
+                entry["nfa_states"] = comp.nsfa_sets()[2]
+            row[kind] = entry
+            del table, comp
+        rows.append(row)
+    return {"rows": rows}
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha1()
@@ -335,7 +395,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of the workload size (counter calibration)")
-    ap.add_argument("--study", choices=["crossover", "rn"], default=None,
+    ap.add_argument("--study", choices=["crossover", "rn", "nsfa"], default=None,
                     help="run a study instead of the benchmark and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -349,6 +409,9 @@ def main():
 
     if args.study == "crossover":
         print(json.dumps({"study": "small-input crossover", **crossover_study(args.seed)}), flush=True)
+        return
+    if args.study == "nsfa":
+        print(json.dumps({"study": "D-SFA and N-SFA", **nsfa_study(args.seed, 1 << 28)}), flush=True)
         return
     if args.study == "rn":
         print(json.dumps({"study": "r_n scalability and placement", **rn_study(args.seed, 1 << 30)}), flush=True)

@@ -111,6 +111,35 @@ sfa_status sfa_compile(const char *pattern, size_t pattern_len, uint32_t sfa_cap
 sfa_status sfa_compiled_info(const sfa_compiled *c, sfa_compile_info *out);
 void       sfa_compiled_free(sfa_compiled *c);
 
+/* N-SFA compilation: the SFA of Definition 3 built from the regex's position
+ * automaton (Glushkov; state 0 initial, states 1.. the byte-set leaves in
+ * left-to-right order with bounded repeats written out), by Algorithm 4
+ * over correspondences f: Q -> P(Q) (Section 5.1); nsfa_cap bounds its
+ * states (0: do not build it; over the cap n_sfa is 0 and sfa_over_cap 1).
+ *   The compiled object has the same shape as a D-SFA compilation, so it is
+ *   loaded with sfa_compiled_desc / sfa_load_table and matched with every
+ *   entry point: its "DFA" is the subset automaton of the NFA (the sets of
+ *   NFA states reachable from I, numbered in breadth-first order over the
+ *   NFA's byte classes), sfa_next is the N-SFA transition table and
+ *   sfa_map[f][S] is the subset U_{q in S} f(q), which is again reachable.
+ *   A match result's state is then the index of S_fin = U_{q in I} f_fin(q)
+ *   (Algorithm 5), and sfa_compiled_nsfa_sets gives the NFA states of every
+ *   index; accept = [S_fin meets F].
+ *   sfa_compile_info.n_dfa counts the subsets, n_sfa the N-SFA states. */
+sfa_status sfa_compile_nsfa(const char *pattern, size_t pattern_len, uint32_t nsfa_cap,
+                            uint32_t dfa_cap, sfa_compiled **out);
+
+typedef struct sfa_nsfa_sets {
+    uint32_t n_nfa;             /* states of the position automaton */
+    uint32_t words;             /* 64-bit words per state set: ceil(n_nfa / 64) */
+    const uint64_t *sets;       /* [n_dfa * words]: bit q of set d = NFA state q is in subset d */
+    const uint64_t *final_set;  /* [words]: F */
+} sfa_nsfa_sets;
+
+/* The subsets of an N-SFA compilation (pointers into c; valid while c
+ * lives).  SFA_ERR_INVALID_ARG for a D-SFA compilation. */
+sfa_status sfa_compiled_nsfa_sets(const sfa_compiled *c, sfa_nsfa_sets *out);
+
 /* Host arrays describing a DFA and (optionally) its D-SFA.
  *   byte_class[256]             class id (< n_classes) of each byte value
  *   dfa_next[n_dfa*n_classes]   delta(q, c) at [q*n_classes + c]

@@ -52,6 +52,11 @@ class LoadOptions(ctypes.Structure):
                 ("profile_sample", ctypes.c_void_p), ("profile_bytes", ctypes.c_uint64)]
 
 
+class NsfaSets(ctypes.Structure):
+    _fields_ = [("n_nfa", ctypes.c_uint32), ("words", ctypes.c_uint32),
+                ("sets", ctypes.POINTER(ctypes.c_uint64)), ("final_set", ctypes.POINTER(ctypes.c_uint64))]
+
+
 class TableInfo(ctypes.Structure):
     _fields_ = [("n_dfa", ctypes.c_uint32), ("n_sfa", ctypes.c_uint32), ("n_classes", ctypes.c_uint32),
                 ("q0", ctypes.c_uint32), ("next_bytes", ctypes.c_uint32), ("map_bytes", ctypes.c_uint32),
@@ -89,6 +94,8 @@ SIGNATURES = {
     "sfa_abi_version": (_U32, []),
     "sfa_compile": (ctypes.c_int, [ctypes.c_char_p, _SZ, _U32, _U32, ctypes.POINTER(_P)]),
     "sfa_compiled_info": (ctypes.c_int, [_P, ctypes.POINTER(CompileInfo)]),
+    "sfa_compile_nsfa": (ctypes.c_int, [ctypes.c_char_p, _SZ, _U32, _U32, ctypes.POINTER(_P)]),
+    "sfa_compiled_nsfa_sets": (ctypes.c_int, [_P, ctypes.POINTER(NsfaSets)]),
     "sfa_compiled_free": (None, [_P]),
     "sfa_compiled_desc": (ctypes.c_int, [_P, ctypes.POINTER(TableDesc)]),
     "sfa_table_device_bytes": (ctypes.c_int, [ctypes.POINTER(TableDesc), ctypes.POINTER(LoadOptions),

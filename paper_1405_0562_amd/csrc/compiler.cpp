@@ -434,7 +434,7 @@ struct VecHash {
 };
 
 RawDfa subset_construction(const Glushkov &g, const Frag &root, const std::vector<uint32_t> &cls,
-                           uint32_t k, uint32_t dfa_cap) {
+                           uint32_t k, uint32_t dfa_cap, std::vector<std::vector<uint64_t>> *sets_out = nullptr) {
     const uint32_t P = (uint32_t)g.sets.size();  // incl. position 0
     const uint32_t W = (P + 63) / 64;
     // class masks over positions
@@ -492,6 +492,7 @@ RawDfa subset_construction(const Glushkov &g, const Frag &root, const std::vecto
         }
     }
     d.n = (uint32_t)states.size();
+    if (sets_out) sets_out->swap(states);
     return d;
 }
 
@@ -792,6 +793,157 @@ extern "C" sfa_status sfa_compile(const char *pattern, size_t pattern_len, uint3
         return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
     }
     *out = c;
+    return SFA_OK;
+}
+
+// N-SFA (Definition 3 on the position automaton, Algorithm 4 with
+// correspondences): states are mappings f: Q -> P(Q) stored as P rows of W
+// words, delta_s(f, c)(q) = U_{p in f(q)} delta(p, c); FIFO worklist,
+// classes ascending, identity = state 0.  For the tables, each state f is
+// also given by its action on the reachable subsets S of the subset
+// automaton, f^(S) = U_{q in S} f(q): with f = f_w, f^(S) = delta_D(S, w)
+// is again reachable, (f . g)^ = g^ o f^, and S_fin = f_fin^(I).  The
+// subset automaton plays the DFA's part, so every matcher applies.
+extern "C" sfa_status sfa_compile_nsfa(const char *pattern, size_t pattern_len, uint32_t nsfa_cap,
+                                       uint32_t dfa_cap, sfa_compiled **out) {
+    if (!out || (!pattern && pattern_len)) return sfa_fail(SFA_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (dfa_cap == 0 || dfa_cap > kMaxDfa) dfa_cap = kMaxDfa;
+    sfa_compiled *c = new (std::nothrow) sfa_compiled();
+    if (!c) return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
+    try {
+        Timer t_dfa;
+        Parser parser(pattern ? pattern : "", pattern_len);
+        int root_id = parser.parse();
+        Glushkov g(parser.nodes);
+        Frag root = g.build(root_id);
+        const uint32_t P = (uint32_t)g.sets.size(), W = (P + 63) / 64;
+        c->n_positions = P - 1;
+        uint32_t k = 0;
+        std::vector<uint32_t> ncls = nfa_byte_classes(g.sets, k);
+        std::vector<std::vector<uint64_t>> subsets;
+        RawDfa raw = subset_construction(g, root, ncls, k, dfa_cap, &subsets);
+        if (k > 256) throw sfa_status(SFA_ERR_INVALID_ARG);
+        c->nsfa = 1;
+        c->n_nfa = P;
+        c->words = W;
+        c->n_dfa = raw.n;
+        c->n_classes = k;
+        c->q0 = 0;
+        for (int b = 0; b < 256; ++b) c->byte_class[b] = (uint8_t)ncls[b];
+        c->dfa_next = raw.delta;
+        c->dfa_accept = raw.accept;
+        c->nfa_sets.resize((size_t)raw.n * W);
+        for (uint32_t d = 0; d < raw.n; ++d) std::copy(subsets[d].begin(), subsets[d].end(), &c->nfa_sets[(size_t)d * W]);
+        c->nfa_final.assign(W, 0);
+        for (uint32_t p : root.last) c->nfa_final[p >> 6] |= 1ull << (p & 63);
+        if (root.nullable) c->nfa_final[0] |= 1;
+        c->dfa_seconds = t_dfa.seconds();
+
+        Timer t_sfa;
+        if (nsfa_cap > 0) {
+            // delta(p, c) as W-word sets
+            std::vector<uint32_t> rep(k, 256);
+            for (int b = 255; b >= 0; --b) rep[ncls[b]] = (uint32_t)b;
+            std::vector<uint64_t> dq((size_t)P * k * W, 0);
+            for (uint32_t p = 0; p < P; ++p) {
+                const std::vector<uint32_t> &succ = p == 0 ? root.first : g.follow[p];
+                for (uint32_t a = 0; a < k; ++a)
+                    for (uint32_t t : succ)
+                        if (g.sets[t].test(rep[a])) dq[((size_t)p * k + a) * W + (t >> 6)] |= 1ull << (t & 63);
+            }
+            const size_t FW = (size_t)P * W;   // words of one correspondence
+            std::vector<uint64_t> maps(FW, 0);
+            for (uint32_t q = 0; q < P; ++q) maps[(size_t)q * W + (q >> 6)] = 1ull << (q & 63);
+            std::unordered_map<std::vector<uint64_t>, uint32_t, VecHash> index;
+            index.emplace(std::vector<uint64_t>(maps.begin(), maps.end()), 0);
+            std::vector<uint32_t> snext;
+            std::vector<uint64_t> tmp(FW);
+            uint32_t m = 1;
+            bool over = false;
+            for (uint32_t s = 0; s < m && !over; ++s) {
+                for (uint32_t a = 0; a < k; ++a) {
+                    std::fill(tmp.begin(), tmp.end(), 0);
+                    const uint64_t *f = &maps[(size_t)s * FW];
+                    for (uint32_t q = 0; q < P; ++q)
+                        for (uint32_t w = 0; w < W; ++w) {
+                            uint64_t bits = f[(size_t)q * W + w];
+                            while (bits) {
+                                const uint32_t p = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                                bits &= bits - 1;
+                                const uint64_t *row = &dq[((size_t)p * k + a) * W];
+                                for (uint32_t x = 0; x < W; ++x) tmp[(size_t)q * W + x] |= row[x];
+                            }
+                        }
+                    auto it = index.find(tmp);
+                    uint32_t id;
+                    if (it == index.end()) {
+                        if (m >= nsfa_cap) {
+                            over = true;
+                            break;
+                        }
+                        id = m++;
+                        index.emplace(tmp, id);
+                        maps.insert(maps.end(), tmp.begin(), tmp.end());
+                    } else {
+                        id = it->second;
+                    }
+                    snext.push_back(id);
+                }
+            }
+            if (over) {
+                c->over_cap = 1;
+                c->n_sfa = 0;
+            } else {
+                // action of every state on the reachable subsets
+                std::unordered_map<std::vector<uint64_t>, uint32_t, VecHash> sub_index;
+                for (uint32_t d = 0; d < raw.n; ++d) sub_index.emplace(subsets[d], d);
+                c->sfa_map.resize((size_t)m * raw.n);
+                std::vector<uint64_t> img(W);
+                for (uint32_t s = 0; s < m; ++s) {
+                    const uint64_t *f = &maps[(size_t)s * FW];
+                    for (uint32_t d = 0; d < raw.n; ++d) {
+                        std::fill(img.begin(), img.end(), 0);
+                        for (uint32_t w = 0; w < W; ++w) {
+                            uint64_t bits = subsets[d][w];
+                            while (bits) {
+                                const uint32_t q = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                                bits &= bits - 1;
+                                for (uint32_t x = 0; x < W; ++x) img[x] |= f[(size_t)q * W + x];
+                            }
+                        }
+                        auto it = sub_index.find(img);
+                        if (it == sub_index.end()) throw sfa_status(SFA_ERR_INVALID_ARG);   // cannot happen
+                        c->sfa_map[(size_t)s * raw.n + d] = it->second;
+                    }
+                }
+                c->n_sfa = m;
+                c->sfa_next.swap(snext);
+            }
+        }
+        c->sfa_seconds = t_sfa.seconds();
+    } catch (const ParseErr &e) {
+        delete c;
+        return sfa_fail(SFA_ERR_PARSE, e.msg);
+    } catch (sfa_status st) {
+        delete c;
+        return sfa_fail(st, st == SFA_ERR_DFA_TOO_LARGE ? "subset automaton exceeds " + std::to_string(dfa_cap) + " states"
+                                                        : "N-SFA construction failed");
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
+    }
+    *out = c;
+    return SFA_OK;
+}
+
+extern "C" sfa_status sfa_compiled_nsfa_sets(const sfa_compiled *c, sfa_nsfa_sets *out) {
+    if (!c || !out) return sfa_fail(SFA_ERR_INVALID_ARG, "null argument");
+    if (!c->nsfa) return sfa_fail(SFA_ERR_INVALID_ARG, "not an N-SFA compilation");
+    out->n_nfa = c->n_nfa;
+    out->words = c->words;
+    out->sets = c->nfa_sets.data();
+    out->final_set = c->nfa_final.data();
     return SFA_OK;
 }
 

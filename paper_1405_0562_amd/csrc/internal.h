@@ -18,6 +18,11 @@ struct sfa_compiled {
     std::vector<uint8_t> dfa_accept;  // [n_dfa]
     std::vector<uint32_t> sfa_next;   // [n_sfa * n_classes]
     std::vector<uint32_t> sfa_map;    // [n_sfa * n_dfa]
+    // N-SFA (built from the position automaton): the "DFA" above is the
+    // reachable subset automaton, each of its states is a set of NFA states
+    uint32_t nsfa = 0, n_nfa = 0, words = 0;
+    std::vector<uint64_t> nfa_sets;   // [n_dfa * words]
+    std::vector<uint64_t> nfa_final;  // [words]
 };
 
 // Record a message for sfa_last_error() and return the status.

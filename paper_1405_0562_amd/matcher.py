@@ -31,14 +31,18 @@ class CompileInfo:
 
 
 class Compiled:
-    """Result of the host compiler: canonical minimal DFA and (if built) its D-SFA."""
+    """Result of the host compiler: canonical minimal DFA and (if built) its D-SFA,
+    or (``nsfa=True``) the subset automaton of the position NFA and its N-SFA."""
 
-    def __init__(self, pattern: str, sfa_cap: int = DEFAULT_SFA_CAP, dfa_cap: int = 0):
+    def __init__(self, pattern: str, sfa_cap: int = DEFAULT_SFA_CAP, dfa_cap: int = 0, nsfa: bool = False):
         self.pattern = pattern
+        self.is_nsfa = nsfa
         raw = pattern.encode("latin-1")
         h = ctypes.c_void_p()
-        check(lib().sfa_compile(raw, len(raw), sfa_cap, dfa_cap, ctypes.byref(h)))
+        entry = lib().sfa_compile_nsfa if nsfa else lib().sfa_compile
+        check(entry(raw, len(raw), sfa_cap, dfa_cap, ctypes.byref(h)))
         self._h = h
+        self._sets = None
         ci = _capi.CompileInfo()
         check(lib().sfa_compiled_info(self._h, ctypes.byref(ci)))
         self.info = CompileInfo(ci.n_dfa, ci.n_sfa, ci.n_classes, ci.q0, ci.n_positions,
@@ -78,8 +82,34 @@ class Compiled:
         }
 
 
+    def nsfa_sets(self) -> tuple[np.ndarray, np.ndarray, int]:
+        """N-SFA compilations: (sets[n_dfa, words] as uint64, final[words], n_nfa)."""
+        if not self.is_nsfa:
+            raise ValueError("not an N-SFA compilation")
+        if self._sets is None:
+            s = _capi.NsfaSets()
+            check(lib().sfa_compiled_nsfa_sets(self._h, ctypes.byref(s)))
+            n, w = self.info.n_dfa, s.words
+            sets = np.ctypeslib.as_array(s.sets, shape=(n * w,)).copy().reshape(n, w)
+            final = np.ctypeslib.as_array(s.final_set, shape=(w,)).copy()
+            self._sets = (sets, final, s.n_nfa)
+        return self._sets
+
+    def nsfa_set(self, state: int) -> int:
+        """The NFA states of a result state of an N-SFA match, as a bit mask."""
+        sets, _, _ = self.nsfa_sets()
+        return sum(int(x) << (64 * i) for i, x in enumerate(sets[state]))
+
+
 def compile(pattern: str, sfa_cap: int = DEFAULT_SFA_CAP, dfa_cap: int = 0) -> Compiled:  # noqa: A001
     return Compiled(pattern, sfa_cap, dfa_cap)
+
+
+def compile_nsfa(pattern: str, nsfa_cap: int = DEFAULT_SFA_CAP, dfa_cap: int = 0) -> Compiled:
+    """N-SFA of the regex's position automaton (Definition 3, Algorithm 4);
+    load and match it like a D-SFA compilation, then read the final NFA
+    state set of a result with ``Compiled.nsfa_set(state)``."""
+    return Compiled(pattern, nsfa_cap, dfa_cap, nsfa=True)
 
 
 def _stream_ptr(stream) -> int:

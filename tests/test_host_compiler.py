@@ -104,3 +104,73 @@ def test_rn_construction_counts_and_speed():
     c = sfa.compile(W.rn_regex(50))
     assert (c.info.n_dfa, c.info.n_sfa) == (101, 10100)
     assert c.info.sfa_seconds < 5.0
+
+
+# --------------------------------------------------------------------------
+# N-SFA compilation (position automaton, correspondences)
+# --------------------------------------------------------------------------
+from oracle import nsfa as ON  # noqa: E402
+
+
+def _nsfa_table_result(arr, c, w: bytes):
+    f = 0
+    for b in w:
+        f = arr["sfa_next"][f, arr["byte_class"][b]]
+    q = int(arr["sfa_map"][f, arr["q0"]])
+    return c.nsfa_set(q), bool(arr["dfa_accept"][q])
+
+
+def _check_nsfa(rx, alphabet, rng, words=60):
+    c = sfa.compile_nsfa(rx)
+    a = ON.glushkov(rx)
+    s = ON.build_nsfa(a)
+    assert c.info.n_sfa == s.m and c.info.n_positions + 1 == a.n, rx
+    sets, final, n_nfa = c.nsfa_sets()
+    assert n_nfa == a.n and c.nsfa_set(0) == a.initial
+    assert sum(int(x) << (64 * i) for i, x in enumerate(final)) == a.final
+    arr = c.arrays()
+    assert list(arr["sfa_map"][0]) == list(range(c.info.n_dfa))      # state 0 is the identity
+    for _ in range(words):
+        w = bytes(rng.choice(alphabet) for _ in range(rng.randrange(0, 50)))
+        want = ON.nfa_run(a, w)
+        assert _nsfa_table_result(arr, c, w) == (want, bool(want & a.final)), (rx, w)
+
+
+@pytest.mark.parametrize("rx", ["(ab)*", W.REGEX_C1, W.REGEX_C2, ".*abc.*", "(a|bc)*c", "", "a?b?c?",
+                                W.rn_regex(3)])
+def test_nsfa_named_regexes_equal_oracle(rx):
+    _check_nsfa(rx, b"abc0123456789", random.Random(2))
+
+
+def test_nsfa_workload_families_equal_oracle():
+    rng = random.Random(5)
+    for rx in W.c4_regexes(0) + W.c5_regexes(1)[:6]:
+        _check_nsfa(rx, W.ALPHABET_C4, rng, words=20)
+
+
+def test_nsfa_random_regexes_equal_oracle():
+    rng = random.Random(11)
+    done = 0
+    while done < 40:
+        rx = random_regex(rng, "abc", depth=3)
+        try:
+            s = ON.build_nsfa(ON.glushkov(rx), cap=3000)
+        except ON.OverCap:
+            continue
+        _check_nsfa(rx, b"abcd", rng, words=15)
+        done += 1
+
+
+def test_nsfa_cap_and_sets_of_a_dsfa():
+    c = sfa.compile_nsfa(W.REGEX_C2, nsfa_cap=10)
+    assert c.info.n_sfa == 0 and c.info.sfa_over_cap
+    # the subset automaton remains (for the speculative matcher)
+    arr = c.arrays()
+    w = b"ab" * 50 + b"aabbb"
+    q = 0
+    for b in w:
+        q = arr["dfa_next"][q, arr["byte_class"][b]]
+    a = ON.glushkov(W.REGEX_C2)
+    assert c.nsfa_set(int(q)) == ON.nfa_run(a, w)
+    with pytest.raises(ValueError):
+        sfa.compile(W.REGEX_C2).nsfa_sets()

@@ -499,6 +499,7 @@ def main():
     if not args.no_cpu:
         cpu, want = cpu_baseline(rx, host, args.cpu_budget)
     kname = "k_sfa_lds" if use_sfa and table.info["table_in_lds"] else ("k_sfa_global" if use_sfa else "k_spec_walk")
+    traffic = recorded_traffic(args.workload, kname)   # HBM bytes per launch (scaled PMC), or None
     del bufs
     torch.cuda.empty_cache()
     batching = None if args.no_batch else batching_leg(args.seed, args.batch_docs, min(250, args.batch_docs))
@@ -523,7 +524,10 @@ def main():
                    "n_dfa": comp.info.n_dfa, "n_sfa": comp.info.n_sfa, "n_classes": comp.info.n_classes,
                    "table_in_lds": table.info["table_in_lds"], "path": "sfa" if use_sfa else "speculative"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args.workload, kname),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_over_algorithmic": (traffic / n) if traffic else None,
+                     "traffic_gbs": (traffic / (kern_avg_ms * 1e-3) / 1e9) if traffic else None,
                      "kernel": kname, "kernel_avg_ms": kern_avg_ms,
                      "algorithmic_bytes_per_launch": n,
                      "stream_read_reference": ref,

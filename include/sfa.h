@@ -261,11 +261,16 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  *   block_threads    TB: threads per block (256, 512, 1024).
  *   lanes_per_chunk  consecutive lanes that share a chunk (power of two
  *               <= 16); the chunk is cut into lanes_per_chunk * K pieces.
- * Supported (K, G, D, TB): TB=256: (1,64,2) (1,128,2) (1,128,4) (2,64,2)
- * (2,64,4) (2,128,2) (4,64,2) (8,32,2); TB=512: (1,64,2) (1,128,2) (2,64,2)
- * (2,128,2) (4,32,2) (4,64,2); TB=1024: (1,32,2) (1,64,2) (1,128,2) (2,32,2)
- * (2,64,2).  Tables in global memory use TB=256, lanes_per_chunk=1 and
- * K in {1,2,4,8}.  Other values give SFA_ERR_INVALID_ARG. */
+ * Supported (K, G, D, TB) for tables in LDS: TB=256: (1,64,2) (1,128,2)
+ * (1,128,4) (2,64,2) (2,64,4) (2,128,2) (2,128,3) (2,128,4) (3,128,3)
+ * (4,64,2) (8,32,2); TB=512: (1,64,2) (1,128,2) (2,64,2) (2,128,2) (4,32,2)
+ * (4,64,2); TB=1024: (1,32,2) (1,64,2) (1,128,2) (2,32,2) (2,64,2).  The
+ * default is (2,128,4,256).  Tables in global memory use lanes_per_chunk=1
+ * with TB=256: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3) (4,32,4) (8,16,2)
+ * (8,16,3) (8,16,4); TB=512: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3)
+ * (4,32,4); TB=1024: (1,64,2) (2,64,2); default (4,32,2,512).  With
+ * n_chunks = 0 the default chunk count is one block of lanes per CU.
+ * Other values give SFA_ERR_INVALID_ARG.  Short chunks lower K first. */
 typedef struct sfa_plan {
     uint32_t stride;
     uint32_t pieces;

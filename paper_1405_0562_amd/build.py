@@ -18,6 +18,10 @@ FLAGS = [
     "--offload-arch=gfx950",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the walk loops are unrolled in full (ring buffers indexed by constants
+    # stay in registers); the global-table walk's body exceeds the default
+    # limit for such loops
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-Wall", "-Wno-unused-result",
 ]
 

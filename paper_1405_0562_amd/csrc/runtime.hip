@@ -57,6 +57,7 @@ extern "C" const char *sfa_status_string(sfa_status s) {
 namespace {
 
 constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
+constexpr uint32_t kGlobalBlock = 512;       // default threads per block of the global-table walk
 constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
 constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
 constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
@@ -227,10 +228,68 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
     return L;
 }
 
-// Permutation of D-SFA ids by visit count in a profiling walk (identity
-// stays 0; then descending count, ties by id).  The walk follows the sample
-// bytes (256 walkers over consecutive parts) or, without a sample, classes
-// drawn uniformly (256 walkers x 2048 steps, xorshift generator).
+// States of the small closed sets of the D-SFA's transition graph: strongly
+// connected components with no edge leaving them, of at most kTrapScc states.
+// A walk that enters one never leaves it, so it spends the rest of its chunk
+// there, while a profiling walk may never reach it (the constant mapping to
+// an accepting sink, entered once a keyword has been read, is the usual
+// case).  Iterative Tarjan over the n_sfa x C graph; components in the order
+// they complete.
+constexpr uint32_t kTrapScc = 64, kTrapTotal = 1024;
+
+std::vector<uint32_t> trap_states(const sfa_table_desc *d) {
+    const uint32_t m = d->n_sfa, C = d->n_classes, none = ~0u;
+    std::vector<uint32_t> index(m, none), low(m, 0), stack, out;
+    std::vector<uint8_t> on(m, 0);
+    std::vector<std::pair<uint32_t, uint32_t>> call;   // (state, next class to visit)
+    uint32_t next_index = 0;
+    for (uint32_t root = 0; root < m && out.size() < kTrapTotal; ++root) {
+        if (index[root] != none) continue;
+        call.push_back({root, 0});
+        index[root] = low[root] = next_index++;
+        stack.push_back(root);
+        on[root] = 1;
+        while (!call.empty()) {
+            auto &[v, c] = call.back();
+            if (c < C) {
+                const uint32_t w = d->sfa_next[(uint64_t)v * C + c++];
+                if (index[w] == none) {
+                    index[w] = low[w] = next_index++;
+                    stack.push_back(w);
+                    on[w] = 1;
+                    call.push_back({w, 0});
+                } else if (on[w]) {
+                    low[v] = std::min(low[v], index[w]);
+                }
+                continue;
+            }
+            const uint32_t done = v;
+            call.pop_back();
+            if (!call.empty()) low[call.back().first] = std::min(low[call.back().first], low[done]);
+            if (low[done] != index[done]) continue;
+            // done is the root of a component: pop it, then test that every edge stays inside
+            size_t first = stack.size();
+            while (stack[first - 1] != done) --first;
+            --first;
+            std::vector<uint32_t> comp(stack.begin() + first, stack.end());
+            stack.resize(first);
+            bool closed = comp.size() <= kTrapScc;
+            for (uint32_t q : comp) on[q] = 2;      // 2: in the component being tested
+            for (size_t i = 0; closed && i < comp.size(); ++i)
+                for (uint32_t cc = 0; cc < C; ++cc)
+                    if (on[d->sfa_next[(uint64_t)comp[i] * C + cc]] != 2) { closed = false; break; }
+            for (uint32_t q : comp) on[q] = 0;
+            if (closed && out.size() + comp.size() <= kTrapTotal) out.insert(out.end(), comp.begin(), comp.end());
+        }
+    }
+    return out;
+}
+
+// Permutation of D-SFA ids for the hot-row walk: identity stays 0; then the
+// states of the small closed sets above; then the rest by visit count in a
+// profiling walk (descending, ties by id).  The walk follows the sample bytes
+// (256 walkers over consecutive parts) or, without a sample, classes drawn
+// uniformly (256 walkers x 2048 steps, xorshift generator).
 std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_options *o) {
     const uint32_t m = d->n_sfa, C = d->n_classes;
     std::vector<uint64_t> count(m, 0);
@@ -258,6 +317,10 @@ std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_option
             }
         }
     }
+    // closed sets rank above every visited state (a count no walk reaches)
+    const uint64_t top = ~0ull;
+    const std::vector<uint32_t> traps = trap_states(d);
+    for (size_t i = 0; i < traps.size(); ++i) count[traps[i]] = top - i;
     std::vector<uint32_t> ids(m);
     for (uint32_t i = 0; i < m; ++i) ids[i] = i;
     std::stable_sort(ids.begin() + 1, ids.end(), [&](uint32_t a, uint32_t b) { return count[a] > count[b]; });
@@ -522,7 +585,7 @@ __device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, u
 // mapping rows are read from LDS (copied over the walk-table region) when
 // they fit.
 template <typename MT>
-__device__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t *s_ids, uint32_t E,
+__device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t *s_ids, uint32_t E,
                               uint32_t *scratch, uint16_t *__restrict__ out_map) {
     const uint32_t n = a.n_dfa, G = a.groups, R = E / G;
     uint32_t *target = scratch;
@@ -558,7 +621,7 @@ __device__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t 
 // applied to x, in G groups.  With `out` the whole composed mapping is
 // written there (u16); otherwise thread 0 returns its value at q0.
 template <typename Get>
-__device__ uint32_t compose_rows(Get get, uint32_t count, uint32_t G, uint32_t n, uint32_t q0, uint32_t *scratch,
+__device__ __forceinline__ uint32_t compose_rows(Get get, uint32_t count, uint32_t G, uint32_t n, uint32_t q0, uint32_t *scratch,
                                  uint16_t *out) {
     uint32_t x = q0;
     if (G == 1) {
@@ -583,7 +646,7 @@ __device__ uint32_t compose_rows(Get get, uint32_t count, uint32_t G, uint32_t n
 
 // Composes `count` stored mappings (u16 rows of a.map_stride entries, text
 // order) starting at src; staged: the rows are first copied to LDS offset 0.
-__device__ uint32_t compose_stored(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, const uint16_t *src,
+__device__ __forceinline__ uint32_t compose_stored(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, const uint16_t *src,
                                    uint32_t count, uint32_t G, uint32_t staged, uint16_t *out) {
     const uint32_t n = a.n_dfa, ns = a.map_stride;
     if (staged) {
@@ -610,7 +673,7 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 // release in every wave would write the L2 back once per wave.  The last
 // block takes an agent-scope acquire.  s_last is one LDS word used for
 // nothing else.
-__device__ bool arrive(uint32_t *counter, uint32_t count, uint32_t *s_last) {
+__device__ __forceinline__ bool arrive(uint32_t *counter, uint32_t count, uint32_t *s_last) {
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -631,7 +694,7 @@ __device__ bool arrive(uint32_t *counter, uint32_t count, uint32_t *s_last) {
 // and applies the result to q0.  Two levels: the last block of each run of
 // super_blocks consecutive blocks composes the run into a group mapping, and
 // the last run to finish composes the group mappings.
-__device__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, uint32_t *s_last) {
+__device__ __forceinline__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, uint32_t *s_last) {
     const uint32_t B = gridDim.x;
     const uint16_t *top = a.block_maps;
     uint32_t top_count = B;
@@ -672,7 +735,7 @@ __device__ __forceinline__ uint32_t wave_product(uint32_t x, const uint8_t *mul,
 
 // Ordered product of the ids held by the block's threads (thread order);
 // the result is valid in thread 0.  s_w: one LDS word per wave.
-__device__ uint32_t block_product(uint32_t x, const uint8_t *mul, uint32_t ns, uint32_t *s_w) {
+__device__ __forceinline__ uint32_t block_product(uint32_t x, const uint8_t *mul, uint32_t ns, uint32_t *s_w) {
     x = wave_product(x, mul, ns);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x / 64] = x;
     __syncthreads();
@@ -685,7 +748,7 @@ __device__ uint32_t block_product(uint32_t x, const uint8_t *mul, uint32_t ns, u
 
 // Ordered product of ids[0 .. count) (global memory); thread t takes a run
 // of consecutive ids.  Valid in thread 0.
-__device__ uint32_t product_of_ids(const uint32_t *ids, uint32_t count, const uint8_t *mul, uint32_t ns,
+__device__ __forceinline__ uint32_t product_of_ids(const uint32_t *ids, uint32_t count, const uint8_t *mul, uint32_t ns,
                                    uint32_t *s_w) {
     const uint32_t c = (count + blockDim.x - 1) / blockDim.x;
     const uint32_t b0 = min(count, threadIdx.x * c), b1 = min(count, b0 + c);
@@ -703,7 +766,7 @@ __device__ uint32_t product_of_ids(const uint32_t *ids, uint32_t count, const ui
 // Grid step of product mode, after block_product (x valid in thread 0): as
 // block_done, with one id per block or run instead of a mapping; the last
 // block applies the final D-SFA state's mapping to q0.
-__device__ void finish_ids(const MatchArgs &a, uint32_t x, const uint8_t *mul, uint32_t *s_w, uint32_t *s_last) {
+__device__ __forceinline__ void finish_ids(const MatchArgs &a, uint32_t x, const uint8_t *mul, uint32_t *s_w, uint32_t *s_last) {
     const uint32_t B = gridDim.x, ns = a.n_sfa;
     if (threadIdx.x == 0) a.block_ids[blockIdx.x] = x;
     const uint32_t *top = a.block_ids;
@@ -936,11 +999,15 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 }
 
 // Global-table walk (tables too large for an LDS image): stride 1, state
-// ids of width NT.  The table's rows 0..hot_rows-1 (the most visited states,
-// after the loader's renumbering) are staged in LDS; other rows are read
-// through L1/L2.
-template <int K, typename NT>
-__global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
+// ids of width NT.  The table's rows 0..hot_rows-1 (the most visited
+// states, after the loader's renumbering) are staged in LDS; other rows are
+// read through L1/L2.  Each byte step reads the next row of all K pieces
+// from LDS at once (offsets clamped into the staged rows, so the K chains
+// overlap), then pieces whose state is not staged reload the row from
+// global memory (rare; exec-masked).  The input is loaded as in the LDS
+// walk: G bytes of each piece per step, loads issued D - 1 steps ahead.
+template <int K, int G, int D, typename NT, int TB>
+__global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint16_t *s_cls = (uint16_t *)smem;            // 512 B
     const uint32_t rb = a.row_bytes, H = a.hot_rows;
@@ -948,71 +1015,144 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
     uint8_t *s_hot = smem + 512;
     uint8_t *s_mul = s_hot + hot_bytes;                     // product table (product mode)
     uint32_t *s_ids = (uint32_t *)(s_mul + a.mul_lds);
-    uint32_t *s_flag = s_ids + K * kBlock;
+    uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
-    for (uint32_t i = threadIdx.x; i < 256; i += kBlock) s_cls[i] = a.cls[i];
+
+    uint64_t c0, c1, pos[K], end[K];
+    lane_pieces<K, G, TB>(a, c0, c1, pos, end);
+    const uint32_t head = c1 > c0 ? (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15) : 0u;
+    uint64_t body[K], nb[K], maxnb = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        body[k] = min(end[k], pos[k] + head);
+        nb[k] = (end[k] - body[k]) / G;
+        maxnb = max(maxnb, nb[k]);
+    }
+    constexpr int V = G / 16;
+    uint4 buf[D][K][V];
+    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
+        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t base = (step < nb[k]) ? body[k] + (uint64_t)G * step : body[0];
+#pragma unroll
+            for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
+        }
+        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
+    };
+#pragma unroll
+    for (int d = 0; d < D - 1; ++d)
+        if ((uint64_t)d < maxnb) issue(buf[d], d);
+
+    for (uint32_t i = threadIdx.x; i < 256; i += TB) s_cls[i] = a.cls[i];
     copy16((uint4 *)s_hot, (const uint4 *)a.img, hot_bytes / 16);
     if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
     __syncthreads();
+
     const uint8_t *__restrict__ tab = a.img;
-    auto step = [&](uint32_t s, uint32_t b) -> uint32_t {
+    const uint32_t lim = hot_bytes >= (uint32_t)sizeof(NT) ? hot_bytes - (uint32_t)sizeof(NT) : 0u;
+    // one byte of one piece (heads and tails)
+    auto step1 = [&](uint32_t s, uint32_t b) -> uint32_t {
         const uint32_t off = __umul24(s, rb) + s_cls[b];
         if (s < H) return *(const NT *)(s_hot + off);
         return *(const NT *)(tab + off);
     };
-    uint64_t c0, c1, pos[K], end[K];
-    lane_pieces<K, 16, kBlock>(a, c0, c1, pos, end);
+    // one byte of every piece.  All K rows are read from LDS (at a clamped
+    // offset); a piece outside the staged rows then takes its row from the
+    // global table through a scalar load, one lane at a time.  Scalar loads
+    // are counted apart from vector loads, so a miss does not wait for the
+    // input loads in flight, as a vector load would (those complete in order).
+    auto stepK = [&](uint32_t (&t)[K], const uint32_t (&col)[K]) {
+        uint32_t off[K], v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) off[k] = __umul24(t[k], rb) + col[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = *(const NT *)(s_hot + min(off[k], lim));
+        uint32_t bits = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) bits |= (t[k] >= H ? 1u : 0u) << k;
+        for (uint64_t m = __ballot(bits != 0); m; m &= m - 1) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(m);
+            const uint32_t lb = __builtin_amdgcn_readlane(bits, l);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (lb & (1u << k)) {
+                    const uint32_t o = __builtin_amdgcn_readlane(off[k], l);
+                    const uint32_t w = *(const __attribute__((address_space(4))) uint32_t *)(tab + (o & ~3u));
+                    const uint32_t x = (w >> (8 * (o & 3u & ~(uint32_t)(sizeof(NT) - 1)))) & (uint32_t)(NT)~0u;
+                    if (__lane_id() == l) v[k] = x;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) t[k] = v[k];
+    };
+
     uint32_t st[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = 0;
     if (c1 > c0) {
-        const uint32_t head = (uint32_t)((16 - ((uintptr_t)(a.in + c0) & 15)) & 15);
         for (uint32_t i = 0; i < head; ++i) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool act = pos[k] < end[k];
-                const uint32_t t = step(st[k], a.in[act ? pos[k] : c0]);
+                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
                 st[k] = act ? t : st[k];
                 pos[k] += act ? 1 : 0;
             }
         }
-        uint64_t nb[K], maxnb = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            nb[k] = (end[k] - pos[k]) / 16;
-            maxnb = max(maxnb, nb[k]);
-        }
         if (maxnb) {
-            uint4 cur[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) cur[k] = *(const uint4 *)(a.in + (nb[k] ? pos[k] : pos[0]));
-            for (uint64_t j = 0; j < maxnb; ++j) {
-                uint4 nxt[K];
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    nxt[k] = *(const uint4 *)(a.in + ((j + 1 < nb[k]) ? pos[k] + 16 * (j + 1) : pos[0]));
+            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
                 uint32_t t[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) t[k] = st[k];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
+                for (int v = 0; v < V; ++v) {
 #pragma unroll
-                    for (int k = 0; k < K; ++k) t[k] = step(t[k], (word_of(cur[k], i >> 2) >> (8 * (i & 3))) & 255u);
+                    for (int d = 0; d < 4; ++d) {
+                        // the class columns of a word's four bytes do not depend on
+                        // the walk: read them before its first step
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            uint32_t col[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) col[k] = s_cls[(word_of(cur[k][v], d) >> (8 * i)) & 255u];
+                            stepK(t, col);
+                        }
+                    }
                 }
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    st[k] = (j < nb[k]) ? t[k] : st[k];
-                    cur[k] = nxt[k];
+                for (int k = 0; k < K; ++k) st[k] = (step < nb[k]) ? t[k] : st[k];
+            };
+            uint64_t j = 0;
+            for (; j + 2 * D - 1 <= maxnb; j += D) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    issue(buf[(d + D - 1) % D], j + d + D - 1);
+                    walk(buf[d], j + d);
+                }
+            }
+            for (; j < maxnb; j += D) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (j + d < maxnb) {
+                        if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
+                        walk(buf[d], j + d);
+                    }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < K; ++k) pos[k] += 16 * nb[k];
+            for (int k = 0; k < K; ++k) pos[k] += (uint64_t)G * nb[k];
         }
-        for (uint32_t i = 0; i < 16; ++i) {
+        // tail: fewer than G bytes per piece
+        uint32_t maxtail = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
+        for (uint32_t i = 0; i < maxtail; ++i) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool act = pos[k] < end[k];
-                const uint32_t t = step(st[k], a.in[act ? pos[k] : c0]);
+                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
                 st[k] = act ? t : st[k];
                 pos[k] += act ? 1 : 0;
             }
@@ -1028,7 +1168,7 @@ __global__ __launch_bounds__(kBlock) void k_sfa_global(MatchArgs a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k];
     __syncthreads();
-    const uint32_t E = K * kBlock;
+    const uint32_t E = K * TB;
     uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
     if (a.n_dfa <= 256)
         compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
@@ -1109,6 +1249,23 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
     X(2, 128, 2, 256) X(2, 128, 3, 256) X(2, 128, 4, 256) X(3, 128, 3, 256) X(4, 64, 2, 256) X(8, 32, 2, 256) \
     X(1, 64, 2, 512) X(1, 128, 2, 512) X(2, 64, 2, 512) X(2, 128, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
     X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
+
+// Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
+// shapes of the global-table walk.  K * G <= 128 keeps a step's stride-1
+// walk unrolled in registers; with 512 (1024) threads a shape fits in 256
+// (128) registers, two (four) waves per SIMD.
+#define SFA_GLOBAL_SHAPES(X) \
+    X(1, 64, 2, 256) X(2, 64, 2, 256) X(2, 64, 3, 256) X(4, 32, 2, 256) X(4, 32, 3, 256) X(4, 32, 4, 256) \
+    X(8, 16, 2, 256) X(8, 16, 3, 256) X(8, 16, 4, 256) \
+    X(1, 64, 2, 512) X(2, 64, 2, 512) X(2, 64, 3, 512) X(4, 32, 2, 512) X(4, 32, 3, 512) X(4, 32, 4, 512) \
+    X(1, 64, 2, 1024) X(2, 64, 2, 1024)
+
+bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
+#define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
+    SFA_GLOBAL_SHAPES(SFA_SHAPE_OK)
+#undef SFA_SHAPE_OK
+    return false;
+}
 
 bool lds_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
 #define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
@@ -1192,9 +1349,16 @@ void plan_grid(Plan &P, uint32_t n_dfa, bool ids) {
 
 sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool speculative, const sfa_plan *user,
                      Plan &P) {
+    // a table without an LDS image is walked by the global-table kernel,
+    // whose default blocks have 512 threads
+    bool any_img = false;
+    for (const Image &im : t->L.img) any_img |= im.present != 0;
+    const bool global_walk = !speculative && !any_img;
     if (n_chunks == 0) {
         const uint64_t target = speculative ? 4096 : 1024;   // bytes per chunk at least
-        const uint64_t max_chunks = (uint64_t)std::max(1u, t->num_cus) * (speculative ? kSpecWaves * 8 : kBlock);
+        // default: one block of lanes per CU
+        const uint64_t per_cu = speculative ? kSpecWaves * 8 : global_walk ? kGlobalBlock : kBlock;
+        const uint64_t max_chunks = (uint64_t)std::max(1u, t->num_cus) * per_cu;
         uint64_t p = std::max<uint64_t>(1, (n + target - 1) / target);
         P.n_chunks = (uint32_t)std::min(p, max_chunks);
     } else {
@@ -1228,13 +1392,17 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         if (LPC == 0 || (LPC & (LPC - 1)) || LPC > 16)
             return sfa_fail(SFA_ERR_INVALID_ARG, "plan lanes_per_chunk must be a power of two <= 16");
         if (S == 0) {
-            // global-table walk: 256-thread blocks, K pieces of 16-byte loads
-            if (!user || !user->pieces) K = 8;
-            if (K != 1 && K != 2 && K != 4 && K != 8) return sfa_fail(SFA_ERR_INVALID_ARG, "plan pieces not supported");
-            G = 16;
-            D = 2;
-            TB = kBlock;
-            LPC = 1;
+            // global-table walk: default (4, 32, 2) with 512 threads (two
+            // waves per SIMD share the staged rows and hide each other's
+            // LDS latency)
+            if (!user || !user->pieces) K = 4;
+            if (!user || !user->load_bytes) G = 32;
+            if (!user || !user->depth) D = 2;
+            if (!user || !user->block_threads) TB = kGlobalBlock;
+            if (LPC != 1)
+                return sfa_fail(SFA_ERR_INVALID_ARG, "the global-table walk uses one lane per chunk");
+            if (!global_shape_ok(K, G, D, TB))
+                return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth) not supported by the global walk");
         } else if (!lds_shape_ok(K, G, D, TB)) {
             return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth, block_threads) not supported");
         }
@@ -1242,13 +1410,14 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         // short chunks: fewer pieces, then fewer lanes per chunk
         while (K > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) {
             K /= 2;
-            if (S && !lds_shape_ok(K, G, D, TB)) {
+            if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB)) {
                 G = 64;
                 D = 2;
             }
         }
         while (LPC > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) LPC /= 2;
-        if (S && !lds_shape_ok(K, G, D, TB)) return sfa_fail(SFA_ERR_INVALID_ARG, "no launch shape for this plan");
+        if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB))
+            return sfa_fail(SFA_ERR_INVALID_ARG, "no launch shape for this plan");
         P.S = S;
         P.K = K;
         P.G = G;
@@ -1284,13 +1453,13 @@ hipError_t dispatch_shape(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint3
 }
 
 template <typename NT>
-hipError_t dispatch_global(uint32_t K, uint32_t blocks, size_t lds, hipStream_t s, const MatchArgs &a) {
-    switch (K) {
-        case 8: return launch(k_sfa_global<8, NT>, blocks, kBlock, lds, s, a);
-        case 4: return launch(k_sfa_global<4, NT>, blocks, kBlock, lds, s, a);
-        case 2: return launch(k_sfa_global<2, NT>, blocks, kBlock, lds, s, a);
-        default: return launch(k_sfa_global<1, NT>, blocks, kBlock, lds, s, a);
-    }
+hipError_t dispatch_global(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
+                           hipStream_t s, const MatchArgs &a) {
+#define SFA_SHAPE_LAUNCH(k, g, d, tb) \
+    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb>, blocks, tb, lds, s, a);
+    SFA_GLOBAL_SHAPES(SFA_SHAPE_LAUNCH)
+#undef SFA_SHAPE_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 sfa_status common_checks(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d_ws, size_t ws_bytes,
@@ -1403,11 +1572,11 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         const uint32_t hot_bytes = ((a.hot_rows * a.row_bytes) + 15) & ~15u;
         a.region_bytes = 512 + hot_bytes;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        const size_t lds = a.region_bytes + a.mul_lds + (size_t)P.K * kBlock * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        const size_t lds = a.region_bytes + a.mul_lds + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
-        if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.blocks, lds, s, a);
-        else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.blocks, lds, s, a);
-        else e = dispatch_global<uint32_t>(P.K, P.blocks, lds, s, a);
+        if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        else e = dispatch_global<uint32_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
     }
     if (e != hipSuccess) return sfa_fail(SFA_ERR_HIP, std::string("walk launch: ") + hipGetErrorString(e));
     return SFA_OK;

@@ -231,6 +231,11 @@ def test_c3_hot_rows_with_profile_sample():
     assert run_table(t, rx, data) == want
     t2 = sfa.load(c)            # profile from uniformly random classes
     assert run_table(t2, rx, data, 4096) == want
+    # a few staged rows: most steps of most pieces read the global table
+    t3 = sfa.load(c, lds_budget=256)
+    assert 0 < t3.info["hot_rows"] <= 4
+    assert run_table(t3, rx, data, 4096) == want
+    assert run_table(t3, rx, data) == want
 
 
 # --------------------------------------------------------------------------
@@ -325,16 +330,24 @@ def test_every_lds_launch_plan(rx, product):
                     assert got == want, (plan, n_chunks)
 
 
+GLOBAL_SHAPES = [(1, 64, 2, 256), (2, 64, 2, 256), (2, 64, 3, 256), (4, 32, 2, 256), (4, 32, 3, 256),
+                 (4, 32, 4, 256), (8, 16, 2, 256), (8, 16, 3, 256), (8, 16, 4, 256),
+                 (1, 64, 2, 512), (2, 64, 2, 512), (2, 64, 3, 512), (4, 32, 2, 512), (4, 32, 3, 512),
+                 (4, 32, 4, 512), (1, 64, 2, 1024), (2, 64, 2, 1024)]
+
+
 @pytest.mark.parametrize("product", [True, False])
 def test_every_global_launch_plan(product):
     rx = W.REGEX_C2
     data = small_text(rx, 43, (2 << 20) + 17)
     want = oracle_result(rx, data)
-    t = sfa.load(sfa.compile(rx), force_global=True, product=product)
-    x = to_device(data)
-    for k in (1, 2, 4, 8):
-        for n_chunks in (0, 1000, 65536):
-            assert sfa.match(t, x, n_chunks=n_chunks, plan=dict(pieces=k)).tolist() == want, (k, n_chunks)
+    for lds_budget in (0, 256):          # all rows staged / only a few rows staged
+        t = sfa.load(sfa.compile(rx), force_global=True, product=product, lds_budget=lds_budget)
+        x = to_device(data)
+        for k, g, d, tb in GLOBAL_SHAPES:
+            for n_chunks in (0, 1000, 65536):
+                plan = dict(pieces=k, load_bytes=g, depth=d, block_threads=tb)
+                assert sfa.match(t, x, n_chunks=n_chunks, plan=plan).tolist() == want, (plan, n_chunks, t.info)
 
 
 def test_dsfa_over_65536_states_uses_32_bit_ids():

@@ -226,13 +226,20 @@ sfa_status sfa_free_table(sfa_table *t);
 /* ------------------------------------------------------------------------
  * Single-stream matching (Algorithm 5, Section 5.2).
  *
- *   d_in[0..n) is split into n_chunks chunks [c*L, min((c+1)*L, n)),
- *   L = ceil(n / n_chunks); chunk c's D-SFA state is computed from f_I and the
- *   chunk results are composed in text order; the result is f_fin(q0).  One
- *   lane owns one chunk and may walk it as several interleaved pieces, which
- *   Theorem 2 allows; n_chunks = 0 lets the library choose.  n_chunks > n is
- *   legal (empty chunks are the identity); n = 0 gives (q0, accept(q0)).
- *   Any alignment of d_in is accepted.
+ *   d_in[0..n) is split into n_chunks consecutive chunks; chunk c's D-SFA
+ *   state is computed from f_I and the chunk results are composed in text
+ *   order; the result is f_fin(q0).  The speculative matcher cuts chunks
+ *   [c*L, min((c+1)*L, n)) with L = ceil(n / n_chunks).  The SFA walk
+ *   rounds L up (to a multiple of the bytes one lane loads per step when
+ *   that lengthens a chunk by at most an eighth, else to a multiple of 16)
+ *   and moves every boundary after the first back by d_in's misalignment,
+ *   so full chunks start 16-byte aligned and hold whole load steps; the
+ *   last chunks may be short or empty.  Any split gives the same result
+ *   (Theorem 2).  One lane owns one chunk (or lanes_per_chunk lanes share
+ *   it) and may walk it as several interleaved pieces; n_chunks = 0 lets
+ *   the library choose.  n_chunks > n is legal (empty chunks are the
+ *   identity); n = 0 gives (q0, accept(q0)).  Any alignment of d_in is
+ *   accepted.
  *
  *   Workspace: sfa_match_workspace_bytes() bytes of device memory (enough
  *   for sfa_match, sfa_match_speculative and sfa_match_ex with any plan at
@@ -263,9 +270,12 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  *               <= 16); the chunk is cut into lanes_per_chunk * K pieces.
  * Supported (K, G, D, TB) for tables in LDS: TB=256: (1,64,2) (1,128,2)
  * (1,128,4) (2,64,2) (2,64,4) (2,128,2) (2,128,3) (2,128,4) (3,128,3)
- * (4,64,2) (8,32,2); TB=512: (1,64,2) (1,128,2) (2,64,2) (2,128,2) (4,32,2)
- * (4,64,2); TB=1024: (1,32,2) (1,64,2) (1,128,2) (2,32,2) (2,64,2).  The
- * default is (2,128,4,256).  Tables in global memory use lanes_per_chunk=1
+ * (4,64,2) (8,32,2); TB=512: (1,64,2) (1,128,2) (1,128,3) (1,128,4) (2,64,2)
+ * (2,64,4) (2,128,2) (2,128,3) (4,32,2) (4,64,2); TB=1024: (1,32,2) (1,64,2) (1,128,2) (2,32,2) (2,64,2).  The
+ * default is (2,128,4,256); for a stride-4 table whose chunks are at most
+ * 4 KiB it is (1,128,2,512) with lanes_per_chunk raised until the lanes fill
+ * one 512-thread block per CU, when ceil(n / n_chunks) is a multiple of
+ * 128 * lanes_per_chunk.  Tables in global memory use lanes_per_chunk=1
  * with TB=256: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3) (4,32,4) (8,16,2)
  * (8,16,3) (8,16,4); TB=512: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3)
  * (4,32,4); TB=1024: (1,64,2) (2,64,2); default (4,32,2,512).  With
@@ -347,6 +357,21 @@ sfa_status sfa_batch_upload(const sfa_batch *b, void *d_ws, size_t ws_bytes, voi
 sfa_status sfa_match_batch(const sfa_batch *b, const uint8_t *d_data, void *d_ws, size_t ws_bytes,
                            sfa_result *d_out /* [n_jobs] */, void *stream);
 void       sfa_batch_free(sfa_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Streaming-read reference (measurement aid, not a matching step).
+ *
+ *   Reads d_in[0..n) once with wave-coalesced 16-byte loads and XORs every
+ *   32-bit word (and the n % 16 tail bytes) into *d_out, so the HBM read
+ *   rate of a read-only kernel can be measured on the same buffer and in
+ *   the same run as the matcher: the matcher reads each input byte once
+ *   (its roofline is this read), and this kernel is that read with nothing
+ *   else.  d_in must be 16-byte aligned; d_out is device memory, and its
+ *   value is the XOR of its old contents and the input words (callers
+ *   clear it first if they want the checksum).  Asynchronous on stream.
+ *   SFA_ERR_INVALID_ARG for a null or misaligned pointer.
+ * ---------------------------------------------------------------------- */
+sfa_status sfa_stream_read(const uint8_t *d_in, uint64_t n, uint32_t *d_out, void *stream);
 
 #ifdef __cplusplus
 }

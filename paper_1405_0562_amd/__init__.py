@@ -9,5 +9,5 @@ finite automata (Sin'ya, Matsuzaki, Sassa, ICPP 2013).
 The matcher is libsfa.so (C ABI in include/sfa.h); this package binds it.
 """
 from ._capi import SfaError, ParseError, lib  # noqa: F401
-from .matcher import Compiled, Table, compile, compile_nsfa, load, match, match_speculative  # noqa: F401
+from .matcher import Compiled, Table, compile, compile_nsfa, load, match, match_speculative, stream_read  # noqa: F401
 from .batch import Autotuner, Batch, BatchOptions, GraphBatch, match_batch  # noqa: F401

@@ -115,6 +115,7 @@ SIGNATURES = {
     "sfa_batch_upload": (ctypes.c_int, [_P, _P, _SZ, _P]),
     "sfa_match_batch": (ctypes.c_int, [_P, _P, _P, _SZ, _P, _P]),
     "sfa_batch_free": (None, [_P]),
+    "sfa_stream_read": (ctypes.c_int, [_P, _U64, _P, _P]),
 }
 
 _lib = None

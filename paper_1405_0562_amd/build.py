@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsfa.so")
 
 HOST_SOURCES = ["compiler.cpp"]
-HIP_SOURCES = ["runtime.hip", "batch.hip"]
+HIP_SOURCES = ["runtime.hip", "batch.hip", "stream.hip"]
 BUILD_DIR = os.path.join(HERE, "_build")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -58,6 +58,7 @@ namespace {
 
 constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
 constexpr uint32_t kGlobalBlock = 512;       // default threads per block of the global-table walk
+constexpr uint64_t kShortChunk = 4096;       // chunk bytes up to which the stride-4 walk uses 512 threads
 constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
 constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
 constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
@@ -510,7 +511,7 @@ using sfa_dev::copy16;
 struct MatchArgs {
     const uint8_t *in;
     uint64_t n;
-    uint64_t chunk_len;      // L = ceil(n / n_chunks)
+    uint64_t chunk_len;      // L >= ceil(n / n_chunks)
     uint32_t n_chunks;
     uint32_t n_dfa;
     uint32_t q0;
@@ -805,12 +806,17 @@ __device__ __forceinline__ void lane_pieces(const MatchArgs &a, uint64_t &c0, ui
     const uint32_t lpc = a.lanes_per_chunk;
     const uint64_t chunk = lane / lpc;
     const uint32_t part = (uint32_t)(lane - chunk * lpc);
-    c0 = a.n;
-    c1 = a.n;
-    if (chunk < a.n_chunks) {
-        c0 = min(a.n, chunk * a.chunk_len);
-        c1 = min(a.n, c0 + a.chunk_len);
-    }
+    // chunk c covers [b(c), b(c + 1)): b(0) = 0, b(c) = c * L - s, b(p) = n.
+    // With L a multiple of 16, s = the input's misalignment puts every chunk
+    // after the first on a 16-byte boundary (any split gives the same
+    // result, Theorem 2 in Section 4.3)
+    const uint64_t L = a.chunk_len;
+    const uint64_t s = (L & 15) ? 0 : (uint64_t)((uintptr_t)a.in & 15);
+    auto bound = [&](uint64_t c) -> uint64_t {
+        return c == 0 ? 0 : c >= a.n_chunks ? a.n : min(a.n, c * L - s);
+    };
+    c0 = chunk < a.n_chunks ? bound(chunk) : a.n;
+    c1 = chunk < a.n_chunks ? bound(chunk + 1) : a.n;
     const uint64_t len = c1 - c0;
     const uint64_t np = (uint64_t)lpc * K;
     const uint64_t piece = (((len + np - 1) / np) + Q - 1) / Q * Q;
@@ -1247,7 +1253,8 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
 #define SFA_LDS_SHAPES(X) \
     X(1, 64, 2, 256) X(1, 128, 2, 256) X(1, 128, 4, 256) X(2, 64, 2, 256) X(2, 64, 4, 256) \
     X(2, 128, 2, 256) X(2, 128, 3, 256) X(2, 128, 4, 256) X(3, 128, 3, 256) X(4, 64, 2, 256) X(8, 32, 2, 256) \
-    X(1, 64, 2, 512) X(1, 128, 2, 512) X(2, 64, 2, 512) X(2, 128, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
+    X(1, 64, 2, 512) X(1, 128, 2, 512) X(1, 128, 3, 512) X(1, 128, 4, 512) X(2, 64, 2, 512) X(2, 64, 4, 512) \
+    X(2, 128, 2, 512) X(2, 128, 3, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
     X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
 
 // Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
@@ -1376,6 +1383,19 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         // ahead (the deepest ring that stays in registers; it hides HBM
         // latency with one wave per SIMD)
         uint32_t K = 2, G = 128, D = 4, TB = 256, LPC = 1;
+        const bool user_shape = user && (user->stride || user->pieces || user->load_bytes || user->depth ||
+                                         user->block_threads || user->lanes_per_chunk);
+        if (!user_shape && S == 4 && !global_walk && P.chunk_len <= kShortChunk) {
+            // chunks of at most 4 KiB that split into whole 128-byte steps per
+            // lane: the walk of one piece per lane is short, so two waves per
+            // SIMD (512-thread blocks) beat more pieces per lane;
+            // lanes_per_chunk fills one block per CU.  (Measured on ragged
+            // chunk lengths it was no faster, and at times slower.)
+            uint32_t lpc = 1;
+            const uint64_t want = (uint64_t)std::max(1u, t->num_cus) * 512;
+            while (lpc < 16 && (uint64_t)P.n_chunks * lpc < want) lpc *= 2;
+            if (P.chunk_len % ((uint64_t)lpc * 128) == 0) K = 1, G = 128, D = 2, TB = 512, LPC = lpc;
+        }
         if (user) {
             if (user->stride) {
                 const int si = stride_index(user->stride);
@@ -1418,6 +1438,14 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         while (LPC > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) LPC /= 2;
         if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB))
             return sfa_fail(SFA_ERR_INVALID_ARG, "no launch shape for this plan");
+        // every piece of a full chunk is whole G-byte load groups when L is a
+        // multiple of LPC * K * G (no byte-at-a-time tail); used when that
+        // lengthens a chunk by at most an eighth, else L is a multiple of 16
+        // (chunk starts stay 16-byte aligned).  Trailing chunks may end up
+        // short or empty.
+        const uint64_t unit = (uint64_t)LPC * K * G;
+        const uint64_t q = P.chunk_len >= 8 * unit ? unit : 16;
+        P.chunk_len = (P.chunk_len + q - 1) / q * q;
         P.S = S;
         P.K = K;
         P.G = G;

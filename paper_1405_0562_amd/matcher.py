@@ -221,6 +221,19 @@ def match(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor
     return _match("sfa_match", table, data, n_chunks, out, stream, plan)
 
 
+def stream_read(data: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """The streaming-read reference kernel: reads ``data`` (uint8, 16-byte
+    aligned, on the device) once and XORs its 32-bit words into ``out``
+    (one int32 on the device).  Used to measure the read-only HBM rate."""
+    if data.dtype != torch.uint8 or not data.is_cuda or not data.is_contiguous():
+        raise ValueError("data must be a contiguous torch.uint8 tensor on the GPU")
+    if out.dtype != torch.int32 or not out.is_cuda or out.numel() < 1:
+        raise ValueError("out must be an int32 tensor on the GPU")
+    check(lib().sfa_stream_read(ctypes.c_void_p(data.data_ptr()), data.numel(), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(_stream_ptr(stream))))
+    return out
+
+
 def match_speculative(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor | None = None,
                       stream=None) -> torch.Tensor:
     """Algorithm 3 on the device; same result as ``match``."""

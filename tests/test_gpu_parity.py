@@ -157,6 +157,27 @@ def test_unaligned_base(offset):
     check(W.REGEX_C1, W.c1_input(offset, n=50_000), n_chunks=33, offset=offset)
 
 
+@pytest.mark.parametrize("offset", [0, 1, 7, 15])
+def test_ragged_sizes_rounded_chunks_and_shifted_boundaries(offset):
+    # the walk rounds the chunk length up to whole load steps and moves the
+    # boundaries back by the base's misalignment: sizes and chunk counts that
+    # are not powers of two, on every plan family, against the sequential scan
+    for rx, data in ((W.REGEX_C2, W.c2_input(30 + offset, n=(1 << 22) + 12_345)),
+                     (W.REGEX_C1, W.c1_input(30 + offset, n=(1 << 21) + 4_002))):
+        want = oracle_result(rx, data)
+        x = to_device(data, offset)
+        c = sfa.compile(rx)
+        for t in (sfa.load(c), sfa.load(c, force_global=True), sfa.load(c, product=False)):
+            for n_chunks in (0, 7, 1000, 4093, 65535, 65536, 131071):
+                say(rx[:20], "offset", offset, "chunks", n_chunks, t.info)
+                assert sfa.match(t, x, n_chunks=n_chunks).tolist() == want, (rx, offset, n_chunks, t.info)
+        t = sfa.load(c)
+        for plan in (dict(pieces=1, load_bytes=128, depth=2, block_threads=512, lanes_per_chunk=2),
+                     dict(pieces=2, load_bytes=128, depth=4), dict(stride=1, pieces=8, load_bytes=32, depth=2)):
+            for n_chunks in (1000, 65535):
+                assert sfa.match(t, x, n_chunks=n_chunks, plan=plan).tolist() == want, (rx, offset, plan)
+
+
 def test_all_byte_values_and_early_sink():
     rng = np.random.default_rng(9)
     data = rng.integers(0, 256, size=1 << 20, dtype=np.uint8)
@@ -308,7 +329,8 @@ def test_product_and_mapping_composition_agree(rx):
 
 LDS_SHAPES = [(1, 64, 2, 256), (1, 128, 2, 256), (1, 128, 4, 256), (2, 64, 2, 256), (2, 64, 4, 256),
               (2, 128, 2, 256), (2, 128, 3, 256), (2, 128, 4, 256), (3, 128, 3, 256), (4, 64, 2, 256), (8, 32, 2, 256),
-              (1, 64, 2, 512), (1, 128, 2, 512), (2, 64, 2, 512), (2, 128, 2, 512), (4, 32, 2, 512), (4, 64, 2, 512),
+              (1, 64, 2, 512), (1, 128, 2, 512), (1, 128, 3, 512), (1, 128, 4, 512), (2, 64, 2, 512), (2, 64, 4, 512),
+              (2, 128, 2, 512), (2, 128, 3, 512), (4, 32, 2, 512), (4, 64, 2, 512),
               (1, 32, 2, 1024), (1, 64, 2, 1024), (1, 128, 2, 1024), (2, 32, 2, 1024), (2, 64, 2, 1024)]
 
 
@@ -365,3 +387,22 @@ def test_dsfa_over_65536_states_uses_32_bit_ids():
         want = oracle_result(rx, data)
         for n_chunks in (0, 1000, 65536):
             assert run_table(t, rx, data, n_chunks) == want, n_chunks
+
+
+@pytest.mark.parametrize("n", [0, 15, 16, 4096 + 7, (1 << 20) + 13, 1 << 24])
+def test_stream_read_reference_reads_every_byte(n):
+    # the streaming-read reference folds every 32-bit word and tail byte of
+    # its input into the XOR checksum; compared with numpy's XOR of the same
+    rng = np.random.default_rng(n)
+    data = rng.integers(0, 256, size=n, dtype=np.uint8)
+    words = np.frombuffer(data[: n - n % 16].tobytes(), dtype=np.uint32)
+    want = int(np.bitwise_xor.reduce(words)) if words.size else 0
+    for b in data[n - n % 16:]:
+        want ^= int(b)
+    x = to_device(data)
+    acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sfa.stream_read(x, acc)
+    assert (int(acc.item()) & 0xFFFFFFFF) == want
+    if n:                           # a misaligned base is rejected by the host, not read
+        with pytest.raises(sfa.SfaError):
+            sfa.stream_read(to_device(data, 1), acc)

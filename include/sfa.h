@@ -277,8 +277,10 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * one 512-thread block per CU, when ceil(n / n_chunks) is a multiple of
  * 128 * lanes_per_chunk.  Tables in global memory use lanes_per_chunk=1
  * with TB=256: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3) (4,32,4) (8,16,2)
- * (8,16,3) (8,16,4); TB=512: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3)
- * (4,32,4); TB=1024: (1,64,2) (2,64,2); default (4,32,2,512).  With
+ * (8,16,3) (8,16,4) (1,128,2) (2,128,2) (4,64,2); TB=512: (1,64,2) (2,64,2)
+ * (2,64,3) (4,32,2) (4,32,3) (4,32,4) (1,128,2) (1,128,3) (1,128,4)
+ * (2,128,2) (2,128,3) (4,64,2); TB=1024: (1,64,2) (2,64,2) (1,128,2);
+ * default (4,64,2,512).  With
  * n_chunks = 0 the default chunk count is one block of lanes per CU.
  * Other values give SFA_ERR_INVALID_ARG.  Short chunks lower K first. */
 typedef struct sfa_plan {

@@ -1258,14 +1258,17 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
     X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
 
 // Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
-// shapes of the global-table walk.  K * G <= 128 keeps a step's stride-1
-// walk unrolled in registers; with 512 (1024) threads a shape fits in 256
-// (128) registers, two (four) waves per SIMD.
+// shapes of the global-table walk; each keeps its load ring in registers
+// (no scratch): with 512 (1024) threads a shape fits in 256 (128)
+// registers, two (four) waves per SIMD.
 #define SFA_GLOBAL_SHAPES(X) \
     X(1, 64, 2, 256) X(2, 64, 2, 256) X(2, 64, 3, 256) X(4, 32, 2, 256) X(4, 32, 3, 256) X(4, 32, 4, 256) \
     X(8, 16, 2, 256) X(8, 16, 3, 256) X(8, 16, 4, 256) \
     X(1, 64, 2, 512) X(2, 64, 2, 512) X(2, 64, 3, 512) X(4, 32, 2, 512) X(4, 32, 3, 512) X(4, 32, 4, 512) \
-    X(1, 64, 2, 1024) X(2, 64, 2, 1024)
+    X(1, 64, 2, 1024) X(2, 64, 2, 1024) \
+    X(1, 128, 2, 256) X(2, 128, 2, 256) X(4, 64, 2, 256) \
+    X(1, 128, 2, 512) X(1, 128, 3, 512) X(1, 128, 4, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) X(4, 64, 2, 512) \
+    X(1, 128, 2, 1024)
 
 bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
 #define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
@@ -1412,11 +1415,12 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         if (LPC == 0 || (LPC & (LPC - 1)) || LPC > 16)
             return sfa_fail(SFA_ERR_INVALID_ARG, "plan lanes_per_chunk must be a power of two <= 16");
         if (S == 0) {
-            // global-table walk: default (4, 32, 2) with 512 threads (two
+            // global-table walk: default (4, 64, 2) with 512 threads (two
             // waves per SIMD share the staged rows and hide each other's
-            // LDS latency)
+            // LDS latency; 64-byte steps visit each 128-byte line twice,
+            // 32-byte steps four times, with lines evicted in between)
             if (!user || !user->pieces) K = 4;
-            if (!user || !user->load_bytes) G = 32;
+            if (!user || !user->load_bytes) G = 64;
             if (!user || !user->depth) D = 2;
             if (!user || !user->block_threads) TB = kGlobalBlock;
             if (LPC != 1)

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "device.h"
+#include "walk.h"
 #include "internal.h"
 
 // ---------------------------------------------------------------------------
@@ -51,37 +51,8 @@ extern "C" const char *sfa_status_string(sfa_status s) {
             return sfa_fail(SFA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// ---------------------------------------------------------------------------
-// device table layout
-// ---------------------------------------------------------------------------
-namespace {
+using namespace sfa_rt;
 
-constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
-constexpr uint32_t kGlobalBlock = 512;       // default threads per block of the global-table walk
-constexpr uint64_t kShortChunk = 4096;       // chunk bytes up to which the stride-4 walk uses 512 threads
-constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
-constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
-constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
-constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K * block threads <= 2048)
-constexpr uint32_t kPairTable = 65536;       // byte-pair class table entries (u8)
-constexpr uint32_t kSpecStage = 16 * 1024;  // speculative blocks: LDS region for the grid composition
-constexpr uint32_t kMulMax = 16 * 1024;      // product table bytes at most (u8 ids: n_sfa <= 128)
-constexpr uint32_t kIdRun = 4096;            // product mode: blocks per level-1 run
-constexpr uint64_t kWsHeader = 4096;         // workspace control words: [0] top level, [1 + r] level-1 run r
-constexpr uint32_t kMaxRuns = kWsHeader / 4 - 1;
-
-inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
-
-// Byte-pair class table layout.  Entry h = b0 | b1 << 8 (b0 first in the
-// text) sits at h with its bits 2..7 XORed with bits 0..5 of b1: the LDS
-// bank of an entry then depends on both bytes, not on b0 alone (text over a
-// small alphabet would otherwise put every lookup of a wave in a few banks).
-// A permutation within each 256-entry block, so the table stays 64 KiB.
-__host__ __device__ inline uint32_t pair_slot(uint32_t h) { return h ^ ((h >> 6) & 0xfcu); }
-// Both pair slots of a 4-byte word at once: low half and high half of the result.
-__host__ __device__ inline uint32_t pair_slots(uint32_t w) { return w ^ ((w >> 6) & 0x00fc00fcu); }
-
-}  // namespace
 
 
 namespace {
@@ -501,687 +472,7 @@ extern "C" sfa_status sfa_free_table(sfa_table *t) {
     return SFA_OK;
 }
 
-// ---------------------------------------------------------------------------
-// kernels
-// ---------------------------------------------------------------------------
 namespace {
-
-using sfa_dev::copy16;
-
-struct MatchArgs {
-    const uint8_t *in;
-    uint64_t n;
-    uint64_t chunk_len;      // L >= ceil(n / n_chunks)
-    uint32_t n_chunks;
-    uint32_t n_dfa;
-    uint32_t q0;
-    uint32_t row_bytes;      // bytes per table row
-    uint32_t one_off;        // LDS walk: byte offset of the single-byte columns
-    uint32_t wide_mul;       // LDS walk, stride 4: C*C (first pair's weight in the column index)
-    uint32_t img_bytes;      // LDS walk: image bytes; speculative: DFA table bytes
-    uint32_t groups;         // G: groups per block in the block composition
-    uint32_t groups1;        // G for a level-1 grid composition (one run of super_blocks blocks)
-    uint32_t final_groups;   // G for the top grid composition
-    uint32_t region_bytes;   // LDS bytes at offset 0 free once the walk is over (multiple of 16)
-    uint32_t map_lds;        // 1: the mapping rows are copied into that region for the block composition
-    uint32_t map_bytes;      // bytes of the mapping rows
-    uint32_t map_stride;     // u16 entries per stored block or group mapping (n_dfa rounded up to 8)
-    uint32_t super_blocks;   // blocks per level-1 run; n_super == 1: one level
-    uint32_t n_super;        // level-1 runs (the top composition composes n_super mappings)
-    uint32_t stage1;         // 1: level-1 compositions stage their block mappings in LDS
-    uint32_t stage2;         // 1: the top composition stages its mappings in LDS
-    uint32_t lanes_per_chunk;  // LPC: consecutive lanes sharing one chunk (walk kernels)
-    uint32_t hot_rows;       // global-table walk: rows 0..hot_rows-1 staged in LDS
-    const uint16_t *cls;     // global walk / speculative: u16[256] class column offsets
-    const uint8_t *img;      // LDS image, global walk table, or u16 DFA table
-    const uint8_t *map;      // mapping rows
-    const uint8_t *accept;   // u8[n_dfa]
-    uint32_t *counter;       // workspace control words: [0] top, [1 + r] level-1 run r
-    uint16_t *block_maps;    // [gridDim.x * map_stride]
-    uint16_t *group_maps;    // [n_super * map_stride] when n_super > 1
-    const uint8_t *mul;      // product table u8[n_sfa * n_sfa] (product mode), else null
-    uint32_t n_sfa;
-    uint32_t mul_lds;        // LDS bytes of the product table copy (multiple of 16); 0: mapping mode
-    uint32_t *block_ids;     // product mode: [gridDim.x] block products
-    uint32_t *run_ids;       // product mode: [n_super] run products
-    sfa_result *out;
-};
-
-// Phase 1 of a composition: the elements 0..E-1 (mappings, in text order) are
-// cut into G groups of R consecutive elements; for every (group g, start
-// state q) pair, q is followed through the group's mappings, the earlier
-// mapping first (reverse composition, f . g = g o f), and the end state is
-// stored at out[g * n + q].  `get(e, x)` is mapping e applied to x.  Four
-// pairs per thread are followed together to hide load latency.
-template <typename Get, typename Out>
-__device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, uint32_t G, uint32_t n,
-                                              Out *out) {
-    const uint32_t items = G * n;
-    for (uint32_t base = threadIdx.x; base < items; base += 4 * blockDim.x) {
-        uint32_t it[4], x[4], e0[4], e1[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            it[i] = min(base + (uint32_t)i * blockDim.x, items - 1);
-            const uint32_t g = it[i] / n;
-            x[i] = it[i] - g * n;
-            e0[i] = g * R;
-            e1[i] = min(E, e0[i] + R);
-        }
-        for (uint32_t r = 0; r < R; ++r) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t e = e0[i] + r;
-                const uint32_t y = get(min(e, E - 1), x[i]);
-                x[i] = e < e1[i] ? y : x[i];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (base + (uint32_t)i * blockDim.x < items) out[it[i]] = x[i];
-    }
-}
-
-// Block composition: the block's E piece states (D-SFA ids in text order,
-// s_ids) become the block mapping M[q], written to out_map (u16).  The
-// mapping rows are read from LDS (copied over the walk-table region) when
-// they fit.
-template <typename MT>
-__device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t *s_ids, uint32_t E,
-                              uint32_t *scratch, uint16_t *__restrict__ out_map) {
-    const uint32_t n = a.n_dfa, G = a.groups, R = E / G;
-    uint32_t *target = scratch;
-    if (a.map_lds) {
-        copy16((uint4 *)smem, (const uint4 *)a.map, (a.map_bytes + 15) / 16);
-        __syncthreads();
-        const MT *m = (const MT *)smem;
-        auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[s_ids[e] * n + x]; };
-        if (G == 1) {
-            follow_groups(get, E, R, 1, n, out_map);
-            return;
-        }
-        follow_groups(get, E, R, G, n, target);
-    } else {
-        const MT *__restrict__ m = (const MT *)a.map;
-        auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[(size_t)s_ids[e] * n + x]; };
-        if (G == 1) {
-            follow_groups(get, E, R, 1, n, out_map);
-            return;
-        }
-        follow_groups(get, E, R, G, n, target);
-    }
-    __syncthreads();
-    // phase 2: every start state through the G group mappings
-    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
-        uint32_t x = q;
-        for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
-        out_map[q] = (uint16_t)x;
-    }
-}
-
-// Composition of `count` mappings in text order, `get(e, x)` being mapping e
-// applied to x, in G groups.  With `out` the whole composed mapping is
-// written there (u16); otherwise thread 0 returns its value at q0.
-template <typename Get>
-__device__ __forceinline__ uint32_t compose_rows(Get get, uint32_t count, uint32_t G, uint32_t n, uint32_t q0, uint32_t *scratch,
-                                 uint16_t *out) {
-    uint32_t x = q0;
-    if (G == 1) {
-        if (out) follow_groups(get, count, count, 1, n, out);
-        else if (threadIdx.x == 0)
-            for (uint32_t e = 0; e < count; ++e) x = get(e, x);
-        return x;
-    }
-    follow_groups(get, count, (count + G - 1) / G, G, n, scratch);
-    __syncthreads();
-    if (out) {
-        for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) {
-            uint32_t y = q;
-            for (uint32_t g = 0; g < G; ++g) y = scratch[g * n + y];
-            out[q] = (uint16_t)y;
-        }
-    } else if (threadIdx.x == 0) {
-        for (uint32_t g = 0; g < G; ++g) x = scratch[g * n + x];
-    }
-    return x;
-}
-
-// Composes `count` stored mappings (u16 rows of a.map_stride entries, text
-// order) starting at src; staged: the rows are first copied to LDS offset 0.
-__device__ __forceinline__ uint32_t compose_stored(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, const uint16_t *src,
-                                   uint32_t count, uint32_t G, uint32_t staged, uint16_t *out) {
-    const uint32_t n = a.n_dfa, ns = a.map_stride;
-    if (staged) {
-        copy16((uint4 *)smem, (const uint4 *)src, count * ns / 8);
-        __syncthreads();
-        const uint16_t *m = (const uint16_t *)smem;
-        return compose_rows([&](uint32_t e, uint32_t y) -> uint32_t { return m[e * ns + y]; }, count, G, n, a.q0,
-                            scratch, out);
-    }
-    const uint16_t *__restrict__ m = src;
-    return compose_rows([&](uint32_t e, uint32_t y) -> uint32_t { return m[(size_t)e * ns + y]; }, count, G, n,
-                        a.q0, scratch, out);
-}
-
-// s_waitcnt immediate that waits for vmcnt(0) only (gfx9 encoding: expcnt
-// and lgkmcnt fields left at their maxima).
-constexpr int kWaitVmcnt0 = 0x0F70;
-
-// Counts this block's arrival at a counter that wraps back to zero after
-// `count` arrivals (atomicInc limit).  True in the last block to arrive,
-// which then sees every earlier block's stores.  Publication: every wave
-// waits until its own stores are acknowledged by the L2, then one wave
-// issues the agent-scope release (an L2 write-back) before the count; a
-// release in every wave would write the L2 back once per wave.  The last
-// block takes an agent-scope acquire.  s_last is one LDS word used for
-// nothing else.
-__device__ __forceinline__ bool arrive(uint32_t *counter, uint32_t count, uint32_t *s_last) {
-    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (threadIdx.x == 0) {
-            const uint32_t prev = atomicInc(counter, count - 1);
-            *s_last = (prev == count - 1) ? 1u : 0u;
-        }
-    }
-    __syncthreads();
-    if (!*s_last) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
-}
-
-// Grid composition, after this block stored its mapping in block_maps.  One
-// level: the last block to finish composes all block mappings in block order
-// and applies the result to q0.  Two levels: the last block of each run of
-// super_blocks consecutive blocks composes the run into a group mapping, and
-// the last run to finish composes the group mappings.
-__device__ __forceinline__ void block_done(const MatchArgs &a, uint8_t *smem, uint32_t *scratch, uint32_t *s_last) {
-    const uint32_t B = gridDim.x;
-    const uint16_t *top = a.block_maps;
-    uint32_t top_count = B;
-    if (a.n_super > 1) {
-        const uint32_t r = blockIdx.x / a.super_blocks, first = r * a.super_blocks;
-        const uint32_t count = min(a.super_blocks, B - first);
-        if (!arrive(a.counter + 1 + r, count, s_last)) return;
-        compose_stored(a, smem, scratch, a.block_maps + (size_t)first * a.map_stride, count, a.groups1, a.stage1,
-                       a.group_maps + (size_t)r * a.map_stride);
-        top = a.group_maps;
-        top_count = a.n_super;
-    }
-    if (!arrive(a.counter, top_count, s_last)) return;
-    const uint32_t x = compose_stored(a, smem, scratch, top, top_count, a.final_groups, a.stage2, nullptr);
-    if (threadIdx.x == 0) {
-        a.out->state = x;
-        a.out->accept = a.accept[x];
-    }
-}
-
-// ---- product mode: chunk results composed as D-SFA ids ------------------
-// mul (LDS) is the n_sfa x n_sfa product table: mul[a * ns + b] is the id
-// of f_a . f_b.  Id 0 is the identity f_I, so padding with 0 is harmless.
-
-// Ordered product x_0 . x_1 . ... . x_63 of the ids held by a wave's lanes
-// (lane order = text order).  Butterfly: at distance o the lane whose bit o
-// is clear holds the left operand; every lane ends with the whole product.
-__device__ __forceinline__ uint32_t wave_product(uint32_t x, const uint8_t *mul, uint32_t ns) {
-    const uint32_t lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_xor((int)x, o, 64);
-        const bool hi = (lane & (uint32_t)o) != 0;
-        x = mul[(hi ? y : x) * ns + (hi ? x : y)];
-    }
-    return x;
-}
-
-// Ordered product of the ids held by the block's threads (thread order);
-// the result is valid in thread 0.  s_w: one LDS word per wave.
-__device__ __forceinline__ uint32_t block_product(uint32_t x, const uint8_t *mul, uint32_t ns, uint32_t *s_w) {
-    x = wave_product(x, mul, ns);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x / 64] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        x = s_w[0];
-        for (uint32_t w = 1; w < blockDim.x / 64; ++w) x = mul[x * ns + s_w[w]];
-    }
-    return x;
-}
-
-// Ordered product of ids[0 .. count) (global memory); thread t takes a run
-// of consecutive ids.  Valid in thread 0.
-__device__ __forceinline__ uint32_t product_of_ids(const uint32_t *ids, uint32_t count, const uint8_t *mul, uint32_t ns,
-                                   uint32_t *s_w) {
-    const uint32_t c = (count + blockDim.x - 1) / blockDim.x;
-    const uint32_t b0 = min(count, threadIdx.x * c), b1 = min(count, b0 + c);
-    uint32_t x = 0;
-    for (uint32_t i = b0; i < b1; i += 8) {
-        uint32_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ids[min(i + u, b1 - 1)];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x = i + u < b1 ? mul[x * ns + v[u]] : x;
-    }
-    return block_product(x, mul, ns, s_w);
-}
-
-// Grid step of product mode, after block_product (x valid in thread 0): as
-// block_done, with one id per block or run instead of a mapping; the last
-// block applies the final D-SFA state's mapping to q0.
-__device__ __forceinline__ void finish_ids(const MatchArgs &a, uint32_t x, const uint8_t *mul, uint32_t *s_w, uint32_t *s_last) {
-    const uint32_t B = gridDim.x, ns = a.n_sfa;
-    if (threadIdx.x == 0) a.block_ids[blockIdx.x] = x;
-    const uint32_t *top = a.block_ids;
-    uint32_t top_count = B;
-    if (a.n_super > 1) {
-        const uint32_t r = blockIdx.x / a.super_blocks, first = r * a.super_blocks;
-        const uint32_t count = min(a.super_blocks, B - first);
-        if (!arrive(a.counter + 1 + r, count, s_last)) return;
-        const uint32_t y = product_of_ids(a.block_ids + first, count, mul, ns, s_w);
-        if (threadIdx.x == 0) a.run_ids[r] = y;
-        top = a.run_ids;
-        top_count = a.n_super;
-    }
-    if (!arrive(a.counter, top_count, s_last)) return;
-    const uint32_t f = product_of_ids(top, top_count, mul, ns, s_w);
-    if (threadIdx.x == 0) {
-        const size_t at = (size_t)f * a.n_dfa + a.q0;
-        const uint32_t q = a.n_dfa <= 256 ? a.map[at] : ((const uint16_t *)a.map)[at];
-        a.out->state = q;
-        a.out->accept = a.accept[q];
-    }
-}
-
-__device__ __forceinline__ uint32_t word_of(const uint4 &v, int d) {
-    return d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
-}
-
-// Chunk bounds of this lane and its K pieces.  LPC consecutive lanes share a
-// chunk: the chunk is cut into LPC * K pieces whose lengths are multiples of
-// Q (so every piece starts at the same alignment) and lane part j of the
-// chunk walks pieces j*K .. j*K + K - 1, i.e. piece order is text order.
-template <int K, int Q, int TB>
-__device__ __forceinline__ void lane_pieces(const MatchArgs &a, uint64_t &c0, uint64_t &c1, uint64_t *pos,
-                                            uint64_t *end) {
-    const uint64_t lane = (uint64_t)blockIdx.x * TB + threadIdx.x;
-    const uint32_t lpc = a.lanes_per_chunk;
-    const uint64_t chunk = lane / lpc;
-    const uint32_t part = (uint32_t)(lane - chunk * lpc);
-    // chunk c covers [b(c), b(c + 1)): b(0) = 0, b(c) = c * L - s, b(p) = n.
-    // With L a multiple of 16, s = the input's misalignment puts every chunk
-    // after the first on a 16-byte boundary (any split gives the same
-    // result, Theorem 2 in Section 4.3)
-    const uint64_t L = a.chunk_len;
-    const uint64_t s = (L & 15) ? 0 : (uint64_t)((uintptr_t)a.in & 15);
-    auto bound = [&](uint64_t c) -> uint64_t {
-        return c == 0 ? 0 : c >= a.n_chunks ? a.n : min(a.n, c * L - s);
-    };
-    c0 = chunk < a.n_chunks ? bound(chunk) : a.n;
-    c1 = chunk < a.n_chunks ? bound(chunk + 1) : a.n;
-    const uint64_t len = c1 - c0;
-    const uint64_t np = (uint64_t)lpc * K;
-    const uint64_t piece = (((len + np - 1) / np) + Q - 1) / Q * Q;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        pos[k] = min(c1, c0 + ((uint64_t)part * K + k) * piece);
-        end[k] = min(c1, pos[k] + piece);
-    }
-}
-
-// LDS walk kernel, stride S (bytes per transition lookup), K pieces per lane,
-// G bytes of each piece loaded per step, loads issued D - 1 steps ahead.  Lane l of block b owns chunk
-// c = b*256 + l; its K piece states (in text order) join the block
-// composition, then the grid composition.
-template <int S, int K, int G, int D, int TB>
-__global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    constexpr uint32_t CLS = (S >= 2) ? kPairTable : 0u;   // byte-class table
-    constexpr uint32_t TAB = CLS + 256;                     // rows
-    const uint32_t img = (a.img_bytes + 15) & ~15u;
-    uint8_t *s_mul = smem + img;                            // product table (product mode)
-    uint32_t *s_ids = (uint32_t *)(smem + img + a.mul_lds);
-    uint32_t *s_flag = s_ids + K * TB;
-    uint32_t *s_scr = s_flag + 4;
-    uint64_t c0, c1, pos[K], end[K];
-    lane_pieces<K, G, TB>(a, c0, c1, pos, end);
-    // head: single bytes up to 16-byte alignment (the same for all pieces);
-    // body[k]: where piece k's 16-byte aligned G-byte groups start
-    const uint32_t head = c1 > c0 ? (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15) : 0u;
-    uint64_t body[K], nb[K], maxnb = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        body[k] = min(end[k], pos[k] + head);
-        nb[k] = (end[k] - body[k]) / G;
-        maxnb = max(maxnb, nb[k]);
-    }
-    // ring of D load buffers: the loads of step j + D - 1 are issued before
-    // step j is walked.  Piece 0 is the longest, so a piece past its last
-    // group re-reads piece 0's first group (discarded).
-    constexpr int V = G / 16;
-    uint4 buf[D][K][V];
-    // With a 2-deep ring the compiler would spread a step's loads over the
-    // walk of the previous step; the 16-byte loads that share a 128-byte line
-    // then reach the L2 microseconds apart and the line is fetched again
-    // after an eviction (measured: 1.19x the input bytes).  Scheduling
-    // barriers keep them together.
-    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
-        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint64_t base = (step < nb[k]) ? body[k] + (uint64_t)G * step : body[0];
-#pragma unroll
-            for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
-        }
-        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
-    };
-    // the first loads go out before the table is staged, so their latency
-    // overlaps the staging
-#pragma unroll
-    for (int d = 0; d < D - 1; ++d)
-        if ((uint64_t)d < maxnb) issue(buf[d], d);
-
-    copy16((uint4 *)smem, (const uint4 *)a.img, img / 16, (blockIdx.x * 613u) % (img / 16));
-    if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
-    __syncthreads();
-
-    const uint32_t one = a.one_off, wide = a.wide_mul;
-    auto row = [&](uint32_t off) -> uint32_t { return *(const uint16_t *)(smem + TAB + off); };
-    // one byte: f <- delta_s[f, class(b)]
-    auto step1 = [&](uint32_t st, uint32_t b) -> uint32_t { return row(st + one + smem[CLS + b]); };
-
-    uint32_t st[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = 0;     // f_I
-
-    if (c1 > c0) {
-        for (uint32_t i = 0; i < head; ++i) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool act = pos[k] < end[k];
-                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
-                st[k] = act ? t : st[k];
-                pos[k] += act ? 1 : 0;
-            }
-        }
-        if (maxnb) {
-            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
-                uint32_t t[K];
-#pragma unroll
-                for (int k = 0; k < K; ++k) t[k] = st[k];
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        if constexpr (S == 1) {
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                uint32_t c[K];
-#pragma unroll
-                                for (int k = 0; k < K; ++k) c[k] = smem[CLS + ((word_of(cur[k][v], d) >> (8 * i)) & 255u)];
-#pragma unroll
-                                for (int k = 0; k < K; ++k) t[k] = row(t[k] + c[k]);
-                            }
-                        } else if constexpr (S == 2) {
-                            uint32_t p0[K], p1[K];
-#pragma unroll
-                            for (int k = 0; k < K; ++k) {
-                                const uint32_t w = pair_slots(word_of(cur[k][v], d));
-                                p0[k] = smem[w & 0xffffu];
-                                p1[k] = smem[w >> 16];
-                            }
-#pragma unroll
-                            for (int k = 0; k < K; ++k) t[k] = row(t[k] + p0[k]);
-#pragma unroll
-                            for (int k = 0; k < K; ++k) t[k] = row(t[k] + p1[k]);
-                        } else {
-                            uint32_t p0[K], p1[K];
-#pragma unroll
-                            for (int k = 0; k < K; ++k) {
-                                const uint32_t w = pair_slots(word_of(cur[k][v], d));
-                                p0[k] = smem[w & 0xffffu];
-                                p1[k] = smem[w >> 16];
-                            }
-#pragma unroll
-                            for (int k = 0; k < K; ++k) t[k] = row(__umul24(p0[k], wide) + p1[k] + t[k]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < K; ++k) st[k] = (step < nb[k]) ? t[k] : st[k];
-            };
-            uint64_t j = 0;
-            // steady state: every issued step exists, no bounds checks
-            for (; j + 2 * D - 1 <= maxnb; j += D) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    issue(buf[(d + D - 1) % D], j + d + D - 1);
-                    walk(buf[d], j + d);
-                }
-            }
-            // last steps
-            for (; j < maxnb; j += D) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    if (j + d < maxnb) {
-                        if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
-                        walk(buf[d], j + d);
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) pos[k] += (uint64_t)G * nb[k];
-        }
-        // tail: fewer than G bytes per piece
-        uint32_t maxtail = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
-        for (uint32_t i = 0; i < maxtail; ++i) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool act = pos[k] < end[k];
-                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
-                st[k] = act ? t : st[k];
-                pos[k] += act ? 1 : 0;
-            }
-        }
-    }
-    const uint32_t rs = a.row_bytes;
-    if (a.mul_lds) {
-        uint32_t x = st[0] / rs;
-#pragma unroll
-        for (int k = 1; k < K; ++k) x = s_mul[x * a.n_sfa + st[k] / rs];
-        finish_ids(a, block_product(x, s_mul, a.n_sfa, s_scr), s_mul, s_scr, s_flag);
-        return;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k] / rs;
-    __syncthreads();   // the walk is over: the image region may be reused
-    const uint32_t E = K * TB;
-    uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
-    if (a.n_dfa <= 256)
-        compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
-    else
-        compose_block<uint16_t>(a, smem, s_ids, E, s_scr, bmap);
-    block_done(a, smem, s_scr, s_flag);
-}
-
-// Global-table walk (tables too large for an LDS image): stride 1, state
-// ids of width NT.  The table's rows 0..hot_rows-1 (the most visited
-// states, after the loader's renumbering) are staged in LDS; other rows are
-// read through L1/L2.  Each byte step reads the next row of all K pieces
-// from LDS at once (offsets clamped into the staged rows, so the K chains
-// overlap), then pieces whose state is not staged reload the row from
-// global memory (rare; exec-masked).  The input is loaded as in the LDS
-// walk: G bytes of each piece per step, loads issued D - 1 steps ahead.
-template <int K, int G, int D, typename NT, int TB>
-__global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint16_t *s_cls = (uint16_t *)smem;            // 512 B
-    const uint32_t rb = a.row_bytes, H = a.hot_rows;
-    const uint32_t hot_bytes = ((H * rb) + 15) & ~15u;
-    uint8_t *s_hot = smem + 512;
-    uint8_t *s_mul = s_hot + hot_bytes;                     // product table (product mode)
-    uint32_t *s_ids = (uint32_t *)(s_mul + a.mul_lds);
-    uint32_t *s_flag = s_ids + K * TB;
-    uint32_t *s_scr = s_flag + 4;
-
-    uint64_t c0, c1, pos[K], end[K];
-    lane_pieces<K, G, TB>(a, c0, c1, pos, end);
-    const uint32_t head = c1 > c0 ? (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15) : 0u;
-    uint64_t body[K], nb[K], maxnb = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        body[k] = min(end[k], pos[k] + head);
-        nb[k] = (end[k] - body[k]) / G;
-        maxnb = max(maxnb, nb[k]);
-    }
-    constexpr int V = G / 16;
-    uint4 buf[D][K][V];
-    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
-        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint64_t base = (step < nb[k]) ? body[k] + (uint64_t)G * step : body[0];
-#pragma unroll
-            for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
-        }
-        if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
-    };
-#pragma unroll
-    for (int d = 0; d < D - 1; ++d)
-        if ((uint64_t)d < maxnb) issue(buf[d], d);
-
-    for (uint32_t i = threadIdx.x; i < 256; i += TB) s_cls[i] = a.cls[i];
-    copy16((uint4 *)s_hot, (const uint4 *)a.img, hot_bytes / 16);
-    if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
-    __syncthreads();
-
-    const uint8_t *__restrict__ tab = a.img;
-    const uint32_t lim = hot_bytes >= (uint32_t)sizeof(NT) ? hot_bytes - (uint32_t)sizeof(NT) : 0u;
-    // one byte of one piece (heads and tails)
-    auto step1 = [&](uint32_t s, uint32_t b) -> uint32_t {
-        const uint32_t off = __umul24(s, rb) + s_cls[b];
-        if (s < H) return *(const NT *)(s_hot + off);
-        return *(const NT *)(tab + off);
-    };
-    // one byte of every piece.  All K rows are read from LDS (at a clamped
-    // offset); a piece outside the staged rows then takes its row from the
-    // global table through a scalar load, one lane at a time.  Scalar loads
-    // are counted apart from vector loads, so a miss does not wait for the
-    // input loads in flight, as a vector load would (those complete in order).
-    auto stepK = [&](uint32_t (&t)[K], const uint32_t (&col)[K]) {
-        uint32_t off[K], v[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) off[k] = __umul24(t[k], rb) + col[k];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = *(const NT *)(s_hot + min(off[k], lim));
-        uint32_t bits = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) bits |= (t[k] >= H ? 1u : 0u) << k;
-        for (uint64_t m = __ballot(bits != 0); m; m &= m - 1) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(m);
-            const uint32_t lb = __builtin_amdgcn_readlane(bits, l);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (lb & (1u << k)) {
-                    const uint32_t o = __builtin_amdgcn_readlane(off[k], l);
-                    const uint32_t w = *(const __attribute__((address_space(4))) uint32_t *)(tab + (o & ~3u));
-                    const uint32_t x = (w >> (8 * (o & 3u & ~(uint32_t)(sizeof(NT) - 1)))) & (uint32_t)(NT)~0u;
-                    if (__lane_id() == l) v[k] = x;
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) t[k] = v[k];
-    };
-
-    uint32_t st[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = 0;
-    if (c1 > c0) {
-        for (uint32_t i = 0; i < head; ++i) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool act = pos[k] < end[k];
-                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
-                st[k] = act ? t : st[k];
-                pos[k] += act ? 1 : 0;
-            }
-        }
-        if (maxnb) {
-            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
-                uint32_t t[K];
-#pragma unroll
-                for (int k = 0; k < K; ++k) t[k] = st[k];
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        // the class columns of a word's four bytes do not depend on
-                        // the walk: read them before its first step
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            uint32_t col[K];
-#pragma unroll
-                            for (int k = 0; k < K; ++k) col[k] = s_cls[(word_of(cur[k][v], d) >> (8 * i)) & 255u];
-                            stepK(t, col);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < K; ++k) st[k] = (step < nb[k]) ? t[k] : st[k];
-            };
-            uint64_t j = 0;
-            for (; j + 2 * D - 1 <= maxnb; j += D) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    issue(buf[(d + D - 1) % D], j + d + D - 1);
-                    walk(buf[d], j + d);
-                }
-            }
-            for (; j < maxnb; j += D) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    if (j + d < maxnb) {
-                        if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
-                        walk(buf[d], j + d);
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) pos[k] += (uint64_t)G * nb[k];
-        }
-        // tail: fewer than G bytes per piece
-        uint32_t maxtail = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
-        for (uint32_t i = 0; i < maxtail; ++i) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool act = pos[k] < end[k];
-                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
-                st[k] = act ? t : st[k];
-                pos[k] += act ? 1 : 0;
-            }
-        }
-    }
-    if (a.mul_lds) {
-        uint32_t x = st[0];
-#pragma unroll
-        for (int k = 1; k < K; ++k) x = s_mul[x * a.n_sfa + st[k]];
-        finish_ids(a, block_product(x, s_mul, a.n_sfa, s_scr), s_mul, s_scr, s_flag);
-        return;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k];
-    __syncthreads();
-    const uint32_t E = K * TB;
-    uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
-    if (a.n_dfa <= 256)
-        compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
-    else
-        compose_block<uint16_t>(a, smem, s_ids, E, s_scr, bmap);
-    block_done(a, smem, s_scr, s_flag);
-}
 
 // Speculative kernel (Algorithm 3).  Wave w of block b walks chunk
 // c = b*4 + w; lane j tracks the states q = j, j+64, ... (T[q] <- delta(T[q], sigma));
@@ -1245,30 +536,6 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
     block_done(a, smem, s_T, s_flag);
 }
 
-// ---------------------------------------------------------------------------
-// host-side launch
-// ---------------------------------------------------------------------------
-// Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
-// shapes of the LDS walk.  K * G * D bounds the load buffers in registers.
-#define SFA_LDS_SHAPES(X) \
-    X(1, 64, 2, 256) X(1, 128, 2, 256) X(1, 128, 4, 256) X(2, 64, 2, 256) X(2, 64, 4, 256) \
-    X(2, 128, 2, 256) X(2, 128, 3, 256) X(2, 128, 4, 256) X(3, 128, 3, 256) X(4, 64, 2, 256) X(8, 32, 2, 256) \
-    X(1, 64, 2, 512) X(1, 128, 2, 512) X(1, 128, 3, 512) X(1, 128, 4, 512) X(2, 64, 2, 512) X(2, 64, 4, 512) \
-    X(2, 128, 2, 512) X(2, 128, 3, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
-    X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
-
-// Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
-// shapes of the global-table walk; each keeps its load ring in registers
-// (no scratch): with 512 (1024) threads a shape fits in 256 (128)
-// registers, two (four) waves per SIMD.
-#define SFA_GLOBAL_SHAPES(X) \
-    X(1, 64, 2, 256) X(2, 64, 2, 256) X(2, 64, 3, 256) X(4, 32, 2, 256) X(4, 32, 3, 256) X(4, 32, 4, 256) \
-    X(8, 16, 2, 256) X(8, 16, 3, 256) X(8, 16, 4, 256) \
-    X(1, 64, 2, 512) X(2, 64, 2, 512) X(2, 64, 3, 512) X(4, 32, 2, 512) X(4, 32, 3, 512) X(4, 32, 4, 512) \
-    X(1, 64, 2, 1024) X(2, 64, 2, 1024) \
-    X(1, 128, 2, 256) X(2, 128, 2, 256) X(4, 64, 2, 256) \
-    X(1, 128, 2, 512) X(1, 128, 3, 512) X(1, 128, 4, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) X(4, 64, 2, 512) \
-    X(1, 128, 2, 1024)
 
 bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
 #define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
@@ -1464,35 +731,6 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
     return SFA_OK;
 }
 
-template <typename F>
-hipError_t launch(F fn, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s, const MatchArgs &a) {
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, s, a);
-    return hipGetLastError();
-}
-
-template <int S>
-hipError_t dispatch_shape(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds, hipStream_t s,
-                          const MatchArgs &a) {
-#define SFA_SHAPE_LAUNCH(k, g, d, tb) \
-    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_lds<S, k, g, d, tb>, blocks, tb, lds, s, a);
-    SFA_LDS_SHAPES(SFA_SHAPE_LAUNCH)
-#undef SFA_SHAPE_LAUNCH
-    return hipErrorInvalidValue;
-}
-
-template <typename NT>
-hipError_t dispatch_global(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
-                           hipStream_t s, const MatchArgs &a) {
-#define SFA_SHAPE_LAUNCH(k, g, d, tb) \
-    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb>, blocks, tb, lds, s, a);
-    SFA_GLOBAL_SHAPES(SFA_SHAPE_LAUNCH)
-#undef SFA_SHAPE_LAUNCH
-    return hipErrorInvalidValue;
-}
 
 sfa_status common_checks(const sfa_table *t, const uint8_t *d_in, uint64_t n, void *d_ws, size_t ws_bytes,
                          sfa_result *d_out, const Plan &P) {

@@ -1,0 +1,7 @@
+// Instantiations of the global-table walk kernel k_sfa_global (Algorithm 5,
+// Section 5.2) for u32 D-SFA state ids, one translation unit per id width.
+#include "walk.h"
+
+namespace sfa_rt {
+SFA_DISPATCH_GLOBAL(uint32_t);
+}  // namespace sfa_rt

@@ -61,6 +61,8 @@ struct Layout {
     uint64_t total = 0;
     uint64_t next_bytes = 0;
     uint32_t hot_rows = 0;   // global-table walk: leading rows of sfa_next staged in LDS
+    uint64_t off_himg = 0;   // global-table walk: hot image (u8 classes[256], (hot_rows + 1) x C u16 entries)
+    uint32_t himg_bytes = 0;
     uint32_t renumbered = 0; // 1: D-SFA ids were renumbered by visit count
 };
 

@@ -7,7 +7,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -52,6 +54,31 @@ extern "C" const char *sfa_status_string(sfa_status s) {
     } while (0)
 
 using namespace sfa_rt;
+
+namespace sfa_rt {
+
+hipError_t prepare_kernel(const void *fn) {
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> ready;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if (ready.count({fn, dev})) return hipSuccess;
+    hipFuncAttributes attr;
+    e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;   // dynamic LDS would not start at 0
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e != hipSuccess) return e;
+    ready.insert({fn, dev});
+    return hipSuccess;
+}
+
+}  // namespace sfa_rt
 
 
 
@@ -186,15 +213,22 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
         im.off = off;
         off = align256(off + bytes);
     }
-    L.total = off;
     const bool any_img = L.img[0].present || L.img[1].present || L.img[2].present;
     if (d->n_sfa && !any_img) {
-        // global-table walk: stage as many leading rows as the budget holds
-        const uint64_t rb = (uint64_t)L.C * L.next_w;
-        const uint64_t hb = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : lds_limit,
-                                               lds_limit > extra + 512 ? lds_limit - extra - 512 : 0);
-        L.hot_rows = (uint32_t)std::min<uint64_t>(d->n_sfa, rb ? hb / rb : 0);
+        // global-table walk: a hot image of as many leading rows as the LDS
+        // (or the caller's budget for the rows) holds, plus the cold row.
+        // Entries are u * C in u16, so (hot_rows + 1) * C <= 65535.
+        const uint64_t rb = 2ull * L.C;
+        const uint64_t room = lds_limit > extra + 256 + rb ? lds_limit - extra - 256 - rb : 0;
+        const uint64_t hb = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : room, room);
+        uint64_t h = std::min<uint64_t>(d->n_sfa, hb / rb);
+        h = std::min<uint64_t>(h, 65535 / L.C - 1);
+        L.hot_rows = (uint32_t)h;
+        L.off_himg = off;
+        L.himg_bytes = (uint32_t)(256 + (h + 1) * rb);
+        off = align256(off + L.himg_bytes);
     }
+    L.total = off;
     const uint32_t rn = o ? o->renumber : 0;
     L.renumbered = d->n_sfa > 1 && (rn == 1 || (rn == 0 && !any_img)) ? 1 : 0;
     return L;
@@ -368,6 +402,18 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
                 row[b] = (uint8_t)d->sfa_next[(uint64_t)row[par[b]] * C + pcls[b]];
             }
         }
+    }
+    if (L.himg_bytes) {
+        // hot image of the global-table walk: class indices, then rows
+        // 0..H-1 and the cold row H, entries u * C (u < H) or H * C
+        const uint32_t H = L.hot_rows, cold = H * C;
+        for (int b = 0; b < 256; ++b) img[L.off_himg + b] = (uint8_t)d->byte_class[b];
+        const uint64_t rows = L.off_himg + 256;
+        for (uint32_t r = 0; r <= H; ++r)
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t u = r < H ? d->sfa_next[(uint64_t)r * C + c] : H;
+                put<uint16_t>(img, rows, (uint64_t)r * C + c, (uint16_t)(u < H ? u * C : cold));
+            }
     }
     for (uint32_t S : {1u, 2u, 4u}) {
         const Image &im = L.img[stride_index(S)];
@@ -581,8 +627,7 @@ uint32_t stage_bytes(const sfa_table *t, const Plan &P, bool speculative) {
     if (speculative) return spec_region(t);
     const uint32_t ids = P.K * P.TB * 4;
     if (P.S) return ((t->L.img[stride_index(P.S)].bytes + 15) & ~15u) + ids;
-    const uint32_t row_bytes = t->L.C * t->L.next_w;
-    return 512 + ((t->L.hot_rows * row_bytes + 15) & ~15u) + ids;
+    return ((t->L.himg_bytes + 15) & ~15u) + ids;
 }
 
 // Grid composition plan: one level when all block mappings fit the staging
@@ -835,12 +880,14 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
             default: e = dispatch_shape<1>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a); break;
         }
     } else {
-        a.img = t->d_base + t->L.off_next;
-        a.cls = (const uint16_t *)(t->d_base + t->L.off_cls);
-        a.row_bytes = t->L.C * t->L.next_w;
+        a.img = t->d_base + t->L.off_himg;
+        a.img_bytes = t->L.himg_bytes;
+        a.gtab = t->d_base + t->L.off_next;
+        a.n_classes = t->L.C;
         a.hot_rows = t->L.hot_rows;
-        const uint32_t hot_bytes = ((a.hot_rows * a.row_bytes) + 15) & ~15u;
-        a.region_bytes = 512 + hot_bytes;
+        a.cold = t->L.hot_rows * t->L.C;
+        a.div_magic = ((1ull << 32) + t->L.C - 1) / t->L.C;
+        a.region_bytes = (t->L.himg_bytes + 15) & ~15u;
         a.map_lds = a.map_bytes <= a.region_bytes;
         const size_t lds = a.region_bytes + a.mul_lds + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");

@@ -49,6 +49,17 @@ __host__ __device__ inline uint32_t pair_slots(uint32_t w) { return w ^ ((w >> 6
 
 using sfa_dev::copy16;
 
+// LDS loads at a byte address of the block's dynamic LDS.  The walk
+// kernels declare no static LDS, so their dynamic LDS starts at address 0
+// (prepare_kernel checks this on the host before a kernel's first launch),
+// and an address built from an integer needs no base: a row offset and a
+// column then fold into one v_add_lshl_u32, and constant offsets into the
+// load's offset field.
+typedef const __attribute__((address_space(3))) uint8_t lds_u8_t;
+typedef const __attribute__((address_space(3))) uint16_t lds_u16_t;
+__device__ __forceinline__ uint32_t lds_u8(uint32_t addr) { return *(lds_u8_t *)(uintptr_t)addr; }
+__device__ __forceinline__ uint32_t lds_u16(uint32_t addr) { return *(lds_u16_t *)(uintptr_t)addr; }
+
 struct MatchArgs {
     const uint8_t *in;
     uint64_t n;
@@ -73,8 +84,12 @@ struct MatchArgs {
     uint32_t stage2;         // 1: the top composition stages its mappings in LDS
     uint32_t lanes_per_chunk;  // LPC: consecutive lanes sharing one chunk (walk kernels)
     uint32_t hot_rows;       // global-table walk: rows 0..hot_rows-1 staged in LDS
-    const uint16_t *cls;     // global walk / speculative: u16[256] class column offsets
-    const uint8_t *img;      // LDS image, global walk table, or u16 DFA table
+    uint32_t n_classes;      // global-table walk: C
+    uint32_t cold;           // global-table walk: H * C, the cold row's state value
+    uint64_t div_magic;      // global-table walk: ceil(2^32 / C)
+    const uint8_t *gtab;     // global-table walk: D-SFA transitions, NT ids [n_sfa * C]
+    const uint16_t *cls;     // speculative: u16[256] class column offsets
+    const uint8_t *img;      // LDS image, hot image of the global walk, or u16 DFA table
     const uint8_t *map;      // mapping rows
     const uint8_t *accept;   // u8[n_dfa]
     uint32_t *counter;       // workspace control words: [0] top, [1 + r] level-1 run r
@@ -425,9 +440,9 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     __syncthreads();
 
     const uint32_t one = a.one_off, wide = a.wide_mul;
-    auto row = [&](uint32_t off) -> uint32_t { return *(const uint16_t *)(smem + TAB + off); };
+    auto row = [&](uint32_t off) -> uint32_t { return lds_u16(TAB + off); };
     // one byte: f <- delta_s[f, class(b)]
-    auto step1 = [&](uint32_t st, uint32_t b) -> uint32_t { return row(st + one + smem[CLS + b]); };
+    auto step1 = [&](uint32_t st, uint32_t b) -> uint32_t { return row(st + one + lds_u8(CLS + b)); };
 
     uint32_t st[K];
 #pragma unroll
@@ -457,7 +472,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
                             for (int i = 0; i < 4; ++i) {
                                 uint32_t c[K];
 #pragma unroll
-                                for (int k = 0; k < K; ++k) c[k] = smem[CLS + ((word_of(cur[k][v], d) >> (8 * i)) & 255u)];
+                                for (int k = 0; k < K; ++k) c[k] = lds_u8(CLS + ((word_of(cur[k][v], d) >> (8 * i)) & 255u));
 #pragma unroll
                                 for (int k = 0; k < K; ++k) t[k] = row(t[k] + c[k]);
                             }
@@ -466,8 +481,8 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
                                 const uint32_t w = pair_slots(word_of(cur[k][v], d));
-                                p0[k] = smem[w & 0xffffu];
-                                p1[k] = smem[w >> 16];
+                                p0[k] = lds_u8(w & 0xffffu);
+                                p1[k] = lds_u8(w >> 16);
                             }
 #pragma unroll
                             for (int k = 0; k < K; ++k) t[k] = row(t[k] + p0[k]);
@@ -478,8 +493,8 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 #pragma unroll
                             for (int k = 0; k < K; ++k) {
                                 const uint32_t w = pair_slots(word_of(cur[k][v], d));
-                                p0[k] = smem[w & 0xffffu];
-                                p1[k] = smem[w >> 16];
+                                p0[k] = lds_u8(w & 0xffffu);
+                                p1[k] = lds_u8(w >> 16);
                             }
 #pragma unroll
                             for (int k = 0; k < K; ++k) t[k] = row(__umul24(p0[k], wide) + p1[k] + t[k]);
@@ -545,25 +560,33 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
     block_done(a, smem, s_scr, s_flag);
 }
 
-// Global-table walk (tables too large for an LDS image): stride 1, state
-// ids of width NT.  The table's rows 0..hot_rows-1 (the most visited
-// states, after the loader's renumbering) are staged in LDS; other rows are
-// read through L1/L2.  Each byte step reads the next row of all K pieces
-// from LDS at once (offsets clamped into the staged rows, so the K chains
-// overlap), then pieces whose state is not staged reload the row from
-// global memory (rare; exec-masked).  The input is loaded as in the LDS
+// Global-table walk, for D-SFAs whose walk image does not fit in LDS
+// (stride 1).  The loader renumbers the states so that the most visited come
+// first and builds a hot image of rows 0..H-1 plus one "cold" row:
+//   [class index of each byte, u8[256]] [H + 1 rows of C u16 entries]
+// A row entry is u * C for a hot target u < H and H * C for any other, and
+// every entry of the cold row is H * C.  A piece keeps its state as
+// t = u * C, so one transition is one LDS load at ((t + class) << 1), and a
+// piece that steps onto a cold state stays on the cold row.  Pieces walk four
+// bytes (one word) at a time this way; a piece that ends the word on the
+// cold row walks the word again from its state at the start of the word
+// through the global table (ids of width NT, n_sfa x C entries), one lane at
+// a time, with scalar loads: those are counted apart from the vector loads
+// of the input ring, which complete in order, so a vector load would also
+// wait for the input in flight.  While its state is cold, a piece keeps
+// t = H * C and the state's id in cid.  The input is loaded as in the LDS
 // walk: G bytes of each piece per step, loads issued D - 1 steps ahead.
 template <int K, int G, int D, typename NT, int TB>
 __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    uint16_t *s_cls = (uint16_t *)smem;            // 512 B
-    const uint32_t rb = a.row_bytes, H = a.hot_rows;
-    const uint32_t hot_bytes = ((H * rb) + 15) & ~15u;
-    uint8_t *s_hot = smem + 512;
-    uint8_t *s_mul = s_hot + hot_bytes;                     // product table (product mode)
-    uint32_t *s_ids = (uint32_t *)(s_mul + a.mul_lds);
+    constexpr uint32_t ROWS = 256;                          // rows follow the class table
+    const uint32_t img = (a.img_bytes + 15) & ~15u;
+    uint8_t *s_mul = smem + img;                            // product table (product mode)
+    uint32_t *s_ids = (uint32_t *)(smem + img + a.mul_lds);
     uint32_t *s_flag = s_ids + K * TB;
     uint32_t *s_scr = s_flag + 4;
+    const uint32_t C = a.n_classes, H = a.hot_rows, cold = a.cold;
+    const uint64_t magic = a.div_magic;                     // ceil(2^32 / C): u = (u * C * magic) >> 32
 
     uint64_t c0, c1, pos[K], end[K];
     lane_pieces<K, G, TB>(a, c0, c1, pos, end);
@@ -577,7 +600,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     }
     constexpr int V = G / 16;
     uint4 buf[D][K][V];
-    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) {
+    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) __attribute__((always_inline)) {
         if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -591,85 +614,127 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     for (int d = 0; d < D - 1; ++d)
         if ((uint64_t)d < maxnb) issue(buf[d], d);
 
-    for (uint32_t i = threadIdx.x; i < 256; i += TB) s_cls[i] = a.cls[i];
-    copy16((uint4 *)s_hot, (const uint4 *)a.img, hot_bytes / 16);
+    copy16((uint4 *)smem, (const uint4 *)a.img, img / 16, (blockIdx.x * 613u) % (img / 16));
     if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
     __syncthreads();
 
-    const uint8_t *__restrict__ tab = a.img;
-    const uint32_t lim = hot_bytes >= (uint32_t)sizeof(NT) ? hot_bytes - (uint32_t)sizeof(NT) : 0u;
-    // one byte of one piece (heads and tails)
-    auto step1 = [&](uint32_t s, uint32_t b) -> uint32_t {
-        const uint32_t off = __umul24(s, rb) + s_cls[b];
-        if (s < H) return *(const NT *)(s_hot + off);
-        return *(const NT *)(tab + off);
+    const uint8_t *__restrict__ tab = a.gtab;
+    auto cls = [&](uint32_t b) __attribute__((always_inline)) -> uint32_t { return lds_u8(b); };
+    auto row = [&](uint32_t t, uint32_t c) __attribute__((always_inline)) -> uint32_t {
+        return lds_u16(ROWS + ((t + c) << 1));
     };
-    // one byte of every piece.  All K rows are read from LDS (at a clamped
-    // offset); a piece outside the staged rows then takes its row from the
-    // global table through a scalar load, one lane at a time.  Scalar loads
-    // are counted apart from vector loads, so a miss does not wait for the
-    // input loads in flight, as a vector load would (those complete in order).
-    auto stepK = [&](uint32_t (&t)[K], const uint32_t (&col)[K]) {
-        uint32_t off[K], v[K];
+    // Scalar walk through the global table: from the state (t, cid) over the
+    // classes cl[0 .. nc-1]; returns the new t and sets id to the new state.
+    auto redo = [&](uint32_t t, uint32_t cid, const uint32_t *cl, int nc, uint32_t &id)
+        __attribute__((always_inline)) -> uint32_t {
+        uint64_t s = t == cold ? cid : (uint32_t)(((uint64_t)t * magic) >> 32);
+        for (int i = 0; i < nc; ++i) {
+            const uint64_t at = (s * C + cl[i]) * sizeof(NT);
+            const uint32_t w = *(const __attribute__((address_space(4))) uint32_t *)(tab + (at & ~3ull));
+            s = (w >> (8 * (uint32_t)(at & 3))) & (uint32_t)(NT)~0u;
+        }
+        id = (uint32_t)s;
+        return s < H ? (uint32_t)s * C : cold;
+    };
+    // Four bytes of every piece (classes c[i][k]): LDS walk, then the pieces
+    // that ended on the cold row walk the word again from its start.
+    auto word = [&](uint32_t (&t)[K], uint32_t (&cid)[K], const uint32_t (&c)[4][K]) __attribute__((always_inline)) {
+        uint32_t t0[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) off[k] = __umul24(t[k], rb) + col[k];
+        for (int k = 0; k < K; ++k) t0[k] = t[k];
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = *(const NT *)(s_hot + min(off[k], lim));
-        uint32_t bits = 0;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int k = 0; k < K; ++k) bits |= (t[k] >= H ? 1u : 0u) << k;
-        for (uint64_t m = __ballot(bits != 0); m; m &= m - 1) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(m);
-            const uint32_t lb = __builtin_amdgcn_readlane(bits, l);
+            for (int k = 0; k < K; ++k) t[k] = row(t[k], c[i][k]);
+        uint64_t any = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any |= __ballot(t[k] == cold);
+        if (any) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (lb & (1u << k)) {
-                    const uint32_t o = __builtin_amdgcn_readlane(off[k], l);
-                    const uint32_t w = *(const __attribute__((address_space(4))) uint32_t *)(tab + (o & ~3u));
-                    const uint32_t x = (w >> (8 * (o & 3u & ~(uint32_t)(sizeof(NT) - 1)))) & (uint32_t)(NT)~0u;
-                    if (__lane_id() == l) v[k] = x;
+                for (uint64_t m = __ballot(t[k] == cold); m; m &= m - 1) {
+                    const uint32_t l = (uint32_t)__builtin_ctzll(m);
+                    uint32_t cl[4], id;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cl[i] = __builtin_amdgcn_readlane(c[i][k], l);
+                    const uint32_t v = redo(__builtin_amdgcn_readlane(t0[k], l), __builtin_amdgcn_readlane(cid[k], l),
+                                            cl, 4, id);
+                    const bool mine = __lane_id() == l;
+                    t[k] = mine ? v : t[k];
+                    cid[k] = mine ? id : cid[k];
                 }
             }
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k) t[k] = v[k];
     };
 
-    uint32_t st[K];
+    uint32_t st[K], sid[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = 0;
-    if (c1 > c0) {
-        for (uint32_t i = 0; i < head; ++i) {
+    for (int k = 0; k < K; ++k) {
+        st[k] = H ? 0u : cold;     // f_I is id 0
+        sid[k] = 0;
+    }
+    // single bytes (unaligned heads, short tails) of the pieces still inside
+    auto singles = [&](uint32_t count) __attribute__((always_inline)) {
+        for (uint32_t i = 0; i < count; ++i) {
+            bool act[K];
+            uint32_t c[K], nt[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const bool act = pos[k] < end[k];
-                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
-                st[k] = act ? t : st[k];
-                pos[k] += act ? 1 : 0;
+                act[k] = pos[k] < end[k];
+                c[k] = cls(a.in[act[k] ? pos[k] : c0]);
+                nt[k] = row(st[k], c[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                for (uint64_t m = __ballot(act[k] && nt[k] == cold); m; m &= m - 1) {
+                    const uint32_t l = (uint32_t)__builtin_ctzll(m);
+                    const uint32_t cl = __builtin_amdgcn_readlane(c[k], l);
+                    uint32_t id;
+                    const uint32_t v = redo(__builtin_amdgcn_readlane(st[k], l), __builtin_amdgcn_readlane(sid[k], l),
+                                            &cl, 1, id);
+                    const bool mine = __lane_id() == l;
+                    nt[k] = mine ? v : nt[k];
+                    sid[k] = mine ? id : sid[k];
+                }
+                st[k] = act[k] ? nt[k] : st[k];
+                pos[k] += act[k] ? 1 : 0;
             }
         }
+    };
+    if (c1 > c0) {
+        singles(head);
         if (maxnb) {
-            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step) {
-                uint32_t t[K];
+            auto classes = [&](uint32_t (&c)[4][K], const uint4 (&cur)[K][V], int w) __attribute__((always_inline)) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) t[k] = st[k];
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
+                    for (int k = 0; k < K; ++k) c[i][k] = cls((word_of(cur[k][w / 4], w % 4) >> (8 * i)) & 255u);
+            };
+            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step_no) __attribute__((always_inline)) {
+                uint32_t t[K], id[K];
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        // the class columns of a word's four bytes do not depend on
-                        // the walk: read them before its first step
+                for (int k = 0; k < K; ++k) t[k] = st[k], id[k] = sid[k];
+                // the class columns of the next word are read while this word is walked
+                uint32_t cc[4][K];
+                classes(cc, cur, 0);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            uint32_t col[K];
+                for (int w = 0; w < 4 * V; ++w) {
+                    uint32_t cn[4][K];
+                    if (w + 1 < 4 * V) classes(cn, cur, w + 1);
+                    word(t, id, cc);
+                    if (w + 1 < 4 * V) {
 #pragma unroll
-                            for (int k = 0; k < K; ++k) col[k] = s_cls[(word_of(cur[k][v], d) >> (8 * i)) & 255u];
-                            stepK(t, col);
-                        }
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int k = 0; k < K; ++k) cc[i][k] = cn[i][k];
                     }
                 }
 #pragma unroll
-                for (int k = 0; k < K; ++k) st[k] = (step < nb[k]) ? t[k] : st[k];
+                for (int k = 0; k < K; ++k) {
+                    const bool in = step_no < nb[k];   // a piece past its last step walked a stand-in
+                    st[k] = in ? t[k] : st[k];
+                    sid[k] = in ? id[k] : sid[k];
+                }
             };
             uint64_t j = 0;
             for (; j + 2 * D - 1 <= maxnb; j += D) {
@@ -695,25 +760,21 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
         uint32_t maxtail = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
-        for (uint32_t i = 0; i < maxtail; ++i) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const bool act = pos[k] < end[k];
-                const uint32_t t = step1(st[k], a.in[act ? pos[k] : c0]);
-                st[k] = act ? t : st[k];
-                pos[k] += act ? 1 : 0;
-            }
-        }
+        singles(maxtail);
     }
-    if (a.mul_lds) {
-        uint32_t x = st[0];
+    // D-SFA ids of the piece states
+    uint32_t ids[K];
 #pragma unroll
-        for (int k = 1; k < K; ++k) x = s_mul[x * a.n_sfa + st[k]];
+    for (int k = 0; k < K; ++k) ids[k] = st[k] == cold ? sid[k] : (uint32_t)(((uint64_t)st[k] * magic) >> 32);
+    if (a.mul_lds) {
+        uint32_t x = ids[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) x = s_mul[x * a.n_sfa + ids[k]];
         finish_ids(a, block_product(x, s_mul, a.n_sfa, s_scr), s_mul, s_scr, s_flag);
         return;
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = st[k];
+    for (int k = 0; k < K; ++k) s_ids[threadIdx.x * K + k] = ids[k];
     __syncthreads();
     const uint32_t E = K * TB;
     uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
@@ -737,24 +798,25 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     X(1, 32, 2, 1024) X(1, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 32, 2, 1024) X(2, 64, 2, 1024)
 
 // Supported (pieces K, load bytes G, prefetch depth D, block threads TB)
-// shapes of the global-table walk; each keeps its load ring in registers
-// (no scratch): with 512 (1024) threads a shape fits in 256 (128)
-// registers, two (four) waves per SIMD.
+// shapes of the global-table walk; each keeps its load ring in registers.
+// 128-byte steps read every input line whole (shorter steps read a line in
+// several visits, between which it may leave the L2).
 #define SFA_GLOBAL_SHAPES(X) \
-    X(1, 64, 2, 256) X(2, 64, 2, 256) X(2, 64, 3, 256) X(4, 32, 2, 256) X(4, 32, 3, 256) X(4, 32, 4, 256) \
-    X(8, 16, 2, 256) X(8, 16, 3, 256) X(8, 16, 4, 256) \
-    X(1, 64, 2, 512) X(2, 64, 2, 512) X(2, 64, 3, 512) X(4, 32, 2, 512) X(4, 32, 3, 512) X(4, 32, 4, 512) \
-    X(1, 64, 2, 1024) X(2, 64, 2, 1024) \
-    X(1, 128, 2, 256) X(2, 128, 2, 256) X(4, 64, 2, 256) \
-    X(1, 128, 2, 512) X(1, 128, 3, 512) X(1, 128, 4, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) X(4, 64, 2, 512) \
-    X(1, 128, 2, 1024)
+    X(1, 64, 2, 256) X(2, 64, 2, 256) X(4, 32, 2, 256) X(4, 64, 2, 256) \
+    X(1, 128, 2, 256) X(2, 128, 2, 256) X(4, 128, 2, 256) \
+    X(1, 64, 2, 512) X(2, 64, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
+    X(1, 128, 2, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) \
+    X(1, 64, 2, 1024) X(2, 64, 2, 1024) X(1, 128, 2, 1024)
+
+// Once per kernel and device (runtime.hip): checks that the kernel has no
+// static LDS (its dynamic LDS starts at address 0, which lds_u8/lds_u16
+// assume) and allows it the device's whole LDS as dynamic LDS.
+hipError_t prepare_kernel(const void *fn);
 
 template <typename F>
 hipError_t launch(F fn, uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s, const MatchArgs &a) {
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = prepare_kernel((const void *)fn);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }

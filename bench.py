@@ -40,6 +40,30 @@ WORKLOADS = {
 }
 
 
+def cached_input(name: str, seed: int, cache_dir: str | None):
+    """make_input, stored as .npy files under cache_dir when given (repeated
+    profiler passes over the same workload then skip the generation)."""
+    import numpy as np
+    if not cache_dir:
+        return make_input(name, seed)
+    os.makedirs(cache_dir, exist_ok=True)
+    base = os.path.join(cache_dir, "%s_seed%d" % (name, seed))
+    try:
+        rx = open(base + ".regex", encoding="latin-1").read()
+        data = np.load(base + ".npy", mmap_mode="r")
+        prof = np.load(base + ".profile.npy") if os.path.exists(base + ".profile.npy") else None
+        return rx, np.ascontiguousarray(data), prof
+    except OSError:
+        pass
+    rx, data, prof = make_input(name, seed)
+    np.save(base + ".npy", data)
+    if prof is not None:
+        np.save(base + ".profile.npy", prof)
+    with open(base + ".regex", "w", encoding="latin-1") as fh:
+        fh.write(rx)
+    return rx, data, prof
+
+
 def make_input(name: str, seed: int):
     """(regex, input bytes, profile sample or None).  The keyword workload's
     table ranks its hot rows by a walk over an independent 1 MiB sample of
@@ -394,7 +418,7 @@ def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0)):
 
 
 def measure(name: str, seed: int, steps: int, warmup: int, copies_arg: int, spec_steps: int,
-            cpu_budget: float, no_cpu: bool) -> dict:
+            cpu_budget: float, no_cpu: bool, cache_dir: str | None = None) -> dict:
     """One single-stream workload: timed sfa_match launches, the
     streaming-read reference, the speculative kernel, and the oracle's
     result over all the bytes (plus its timing when cpu_budget > 0)."""
@@ -402,7 +426,7 @@ def measure(name: str, seed: int, steps: int, warmup: int, copies_arg: int, spec
     import paper_1405_0562_amd as sfa
 
     wl = WORKLOADS[name]
-    rx, host, prof = make_input(name, seed)
+    rx, host, prof = cached_input(name, seed, cache_dir)
     n = host.size
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -520,6 +544,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--speculative-steps", type=int, default=3)
+    ap.add_argument("--input-cache", default=None,
+                    help="directory in which generated inputs are stored and reused (profiler passes)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other single-stream workloads reported beside the headline")
     ap.add_argument("--no-batch", action="store_true")
@@ -563,14 +589,15 @@ def main():
 
     progress("workload %s" % args.workload)
     head = measure(args.workload, args.seed, args.steps, args.warmup, args.copies, args.speculative_steps,
-                   args.cpu_budget, args.no_cpu)
+                   args.cpu_budget, args.no_cpu, args.input_cache)
     extra = {}
     if not args.no_extra:
         for name in ("c2_4g", "c2"):
             if name == args.workload:
                 continue
             progress("workload %s" % name)
-            m = measure(name, args.seed, args.steps, args.warmup, 0, args.speculative_steps, 0.0, args.no_cpu)
+            m = measure(name, args.seed, args.steps, args.warmup, 0, args.speculative_steps, 0.0, args.no_cpu,
+                        args.input_cache)
             extra[name] = {k: m[k] for k in ("value", "ms_per_step", "config", "roofline", "result",
                                              "oracle_result", "parity", "speculative")}
     progress("batching")

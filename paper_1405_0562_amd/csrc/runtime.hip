@@ -214,15 +214,17 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
         off = align256(off + bytes);
     }
     const bool any_img = L.img[0].present || L.img[1].present || L.img[2].present;
-    if (d->n_sfa && !any_img) {
+    if (d->n_sfa && !any_img && L.C <= kGlobalMaxClasses) {
         // global-table walk: a hot image of as many leading rows as the LDS
         // (or the caller's budget for the rows) holds, plus the cold row.
-        // Entries are u * C in u16, so (hot_rows + 1) * C <= 65535.
+        // After the walk the piece ids and the composition scratch reuse the
+        // image's region, so only the product table and the flag word are
+        // kept apart.  Entries are row indices in u16.
         const uint64_t rb = 2ull * L.C;
-        const uint64_t room = lds_limit > extra + 256 + rb ? lds_limit - extra - 256 - rb : 0;
+        const uint64_t keep = ((L.mul_bytes + 15) & ~15u) + 16 + 256 + rb;
+        const uint64_t room = lds_limit > keep ? lds_limit - keep : 0;
         const uint64_t hb = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : room, room);
-        uint64_t h = std::min<uint64_t>(d->n_sfa, hb / rb);
-        h = std::min<uint64_t>(h, 65535 / L.C - 1);
+        const uint64_t h = std::min<uint64_t>({(uint64_t)d->n_sfa, hb / rb, 65535});
         L.hot_rows = (uint32_t)h;
         L.off_himg = off;
         L.himg_bytes = (uint32_t)(256 + (h + 1) * rb);
@@ -404,15 +406,16 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
         }
     }
     if (L.himg_bytes) {
-        // hot image of the global-table walk: class indices, then rows
-        // 0..H-1 and the cold row H, entries u * C (u < H) or H * C
-        const uint32_t H = L.hot_rows, cold = H * C;
-        for (int b = 0; b < 256; ++b) img[L.off_himg + b] = (uint8_t)d->byte_class[b];
+        // hot image of the global-table walk: doubled class indices (the
+        // column byte offsets), then rows 0..H-1 and the cold row H, entries
+        // u (u < H) or H
+        const uint32_t H = L.hot_rows;
+        for (int b = 0; b < 256; ++b) img[L.off_himg + b] = (uint8_t)(2 * d->byte_class[b]);
         const uint64_t rows = L.off_himg + 256;
         for (uint32_t r = 0; r <= H; ++r)
             for (uint32_t c = 0; c < C; ++c) {
                 const uint32_t u = r < H ? d->sfa_next[(uint64_t)r * C + c] : H;
-                put<uint16_t>(img, rows, (uint64_t)r * C + c, (uint16_t)(u < H ? u * C : cold));
+                put<uint16_t>(img, rows, (uint64_t)r * C + c, (uint16_t)std::min(u, H));
             }
     }
     for (uint32_t S : {1u, 2u, 4u}) {
@@ -623,11 +626,23 @@ uint32_t spec_region(const sfa_table *t) {
     return std::max<uint32_t>(512 + ((2 * t->L.n_dfa * t->L.C + 15) & ~15u), kSpecStage);
 }
 
+// LDS of the global-table walk: the hot image's region [0, region), whose
+// end takes the piece ids and the composition scratch once the walk is over,
+// leaving [0, free) for staging.
+struct GlobalLds {
+    uint32_t region, free;
+};
+GlobalLds global_lds(const sfa_table *t, const Plan &P) {
+    const uint32_t tail = P.K * P.TB * 4 + kScratchLds;
+    const uint32_t region = std::max(((t->L.himg_bytes + 15) & ~15u), tail);
+    return {region, region - tail};
+}
+
 uint32_t stage_bytes(const sfa_table *t, const Plan &P, bool speculative) {
     if (speculative) return spec_region(t);
     const uint32_t ids = P.K * P.TB * 4;
     if (P.S) return ((t->L.img[stride_index(P.S)].bytes + 15) & ~15u) + ids;
-    return ((t->L.himg_bytes + 15) & ~15u) + ids;
+    return global_lds(t, P).free;
 }
 
 // Grid composition plan: one level when all block mappings fit the staging
@@ -880,16 +895,20 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
             default: e = dispatch_shape<1>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a); break;
         }
     } else {
+        if (!t->L.himg_bytes)
+            return sfa_fail(SFA_ERR_NO_SFA, "the global-table walk takes at most 128 byte classes; "
+                                            "use sfa_match_speculative");
         a.img = t->d_base + t->L.off_himg;
         a.img_bytes = t->L.himg_bytes;
         a.gtab = t->d_base + t->L.off_next;
         a.n_classes = t->L.C;
         a.hot_rows = t->L.hot_rows;
-        a.cold = t->L.hot_rows * t->L.C;
-        a.div_magic = ((1ull << 32) + t->L.C - 1) / t->L.C;
-        a.region_bytes = (t->L.himg_bytes + 15) & ~15u;
+        a.cold = t->L.hot_rows;
+        const GlobalLds g = global_lds(t, P);
+        a.region_bytes = g.free;
+        a.mul_off = g.region;
         a.map_lds = a.map_bytes <= a.region_bytes;
-        const size_t lds = a.region_bytes + a.mul_lds + (size_t)P.K * P.TB * 4 + 16 + scratch_lds(P, t->L.n_dfa);
+        const size_t lds = (size_t)g.region + a.mul_lds + 16;
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
         if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
         else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);

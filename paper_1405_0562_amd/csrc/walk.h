@@ -24,6 +24,7 @@ constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative b
 constexpr uint32_t kDefaultLdsBudget = 96 * 1024;
 constexpr uint32_t kScratchLds = 16 * 1024;  // LDS for group mappings in the composition
 constexpr uint32_t kMaxIds = 8 * kBlock;     // piece states per block (K * block threads <= 2048)
+constexpr uint32_t kGlobalMaxClasses = 128;  // global-table walk: column byte offsets fit u8
 constexpr uint32_t kPairTable = 65536;       // byte-pair class table entries (u8)
 constexpr uint32_t kSpecStage = 16 * 1024;  // speculative blocks: LDS region for the grid composition
 constexpr uint32_t kMulMax = 16 * 1024;      // product table bytes at most (u8 ids: n_sfa <= 128)
@@ -85,8 +86,8 @@ struct MatchArgs {
     uint32_t lanes_per_chunk;  // LPC: consecutive lanes sharing one chunk (walk kernels)
     uint32_t hot_rows;       // global-table walk: rows 0..hot_rows-1 staged in LDS
     uint32_t n_classes;      // global-table walk: C
-    uint32_t cold;           // global-table walk: H * C, the cold row's state value
-    uint64_t div_magic;      // global-table walk: ceil(2^32 / C)
+    uint32_t cold;           // global-table walk: H, the cold row
+    uint32_t mul_off;        // global-table walk: LDS offset of the product table (then the flag word)
     const uint8_t *gtab;     // global-table walk: D-SFA transitions, NT ids [n_sfa * C]
     const uint16_t *cls;     // speculative: u16[256] class column offsets
     const uint8_t *img;      // LDS image, hot image of the global walk, or u16 DFA table
@@ -561,58 +562,92 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 }
 
 // Global-table walk, for D-SFAs whose walk image does not fit in LDS
-// (stride 1).  The loader renumbers the states so that the most visited come
-// first and builds a hot image of rows 0..H-1 plus one "cold" row:
-//   [class index of each byte, u8[256]] [H + 1 rows of C u16 entries]
-// A row entry is u * C for a hot target u < H and H * C for any other, and
-// every entry of the cold row is H * C.  A piece keeps its state as
-// t = u * C, so one transition is one LDS load at ((t + class) << 1), and a
-// piece that steps onto a cold state stays on the cold row.  Pieces walk four
-// bytes (one word) at a time this way; a piece that ends the word on the
-// cold row walks the word again from its state at the start of the word
-// through the global table (ids of width NT, n_sfa x C entries), one lane at
-// a time, with scalar loads: those are counted apart from the vector loads
-// of the input ring, which complete in order, so a vector load would also
-// wait for the input in flight.  While its state is cold, a piece keeps
-// t = H * C and the state's id in cid.  The input is loaded as in the LDS
-// walk: G bytes of each piece per step, loads issued D - 1 steps ahead.
+// (stride 1, at most 128 byte classes).  The loader renumbers the states so
+// that the most visited come first and builds a hot image of rows 0..H-1
+// plus one "cold" row H:
+//   [2 * class of each byte, u8[256]] [H + 1 rows of C u16 entries]
+// A row entry is the target u when u < H and H otherwise, and every entry of
+// the cold row is H, so one transition is one LDS load at u * 2C + 2 * class,
+// and a piece that steps onto a cold state stays on the cold row.  Pieces
+// walk four bytes (one word) at a time this way; a piece that ends the word
+// on the cold row walks the word again through the global table (ids of
+// width NT, n_sfa x C entries), one lane at a time, with scalar loads: those
+// are counted apart from the vector loads of the input ring, which complete
+// in order, so a vector load would also wait for the input in flight.  While
+// its state is cold, a piece keeps t = H and the state's id in cid.  The
+// input is loaded as in the LDS walk: G bytes of each piece per step, loads
+// issued D - 1 steps ahead.
+//
+// LDS: [0, R) the hot image during the walk; once every wave has finished
+// its walk, the piece ids and the composition scratch take the end of that
+// region ([region_bytes, R)) and [0, region_bytes) is free for staging;
+// [R, R + mul_lds) the product table (product mode); then the flag word.
 template <int K, int G, int D, typename NT, int TB>
 __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr uint32_t ROWS = 256;                          // rows follow the class table
     const uint32_t img = (a.img_bytes + 15) & ~15u;
-    uint8_t *s_mul = smem + img;                            // product table (product mode)
-    uint32_t *s_ids = (uint32_t *)(smem + img + a.mul_lds);
-    uint32_t *s_flag = s_ids + K * TB;
-    uint32_t *s_scr = s_flag + 4;
-    const uint32_t C = a.n_classes, H = a.hot_rows, cold = a.cold;
-    const uint64_t magic = a.div_magic;                     // ceil(2^32 / C): u = (u * C * magic) >> 32
+    uint8_t *s_mul = smem + a.mul_off;                      // product table (product mode)
+    uint32_t *s_ids = (uint32_t *)(smem + a.region_bytes);  // after the walk
+    uint32_t *s_scr = s_ids + K * TB;
+    uint32_t *s_flag = (uint32_t *)(smem + a.mul_off + a.mul_lds);
+    const uint32_t C = a.n_classes, H = a.hot_rows, cold = a.cold, RB = 2 * C;
 
     uint64_t c0, c1, pos[K], end[K];
     lane_pieces<K, G, TB>(a, c0, c1, pos, end);
     const uint32_t head = c1 > c0 ? (uint32_t)((16 - ((uintptr_t)(a.in + pos[0]) & 15)) & 15) : 0u;
-    uint64_t body[K], nb[K], maxnb = 0;
+    // piece k's whole G-byte groups start `body[k]` bytes after c0 (a chunk
+    // is shorter than 4 GiB); 32-bit offsets keep the walk's registers few
+    const uint8_t *const cin = a.in + c0;
+    uint32_t body[K], nb[K], maxnb = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        body[k] = min(end[k], pos[k] + head);
-        nb[k] = (end[k] - body[k]) / G;
+        const uint64_t b0 = min(end[k], pos[k] + head);
+        body[k] = (uint32_t)(b0 - c0);
+        nb[k] = (uint32_t)((end[k] - b0) / G);
         maxnb = max(maxnb, nb[k]);
     }
-    constexpr int V = G / 16;
-    uint4 buf[D][K][V];
-    auto issue = [&](uint4 (&dst)[K][V], uint64_t step) __attribute__((always_inline)) {
+    // D >= 2: a ring of D steps of G bytes per piece, the loads of step j + D
+    // - 1 issued before step j is walked.  D == 1: a rolling ring of three
+    // half-line slots (G / 2 bytes) per piece: line j occupies two slots, and
+    // once its first half is walked the whole of line j + 1 is loaded into
+    // that slot and the spare one, so every line is requested whole (a line
+    // read in two visits may leave the L2 in between) with 1.5 lines of
+    // registers per piece instead of 2.
+    constexpr int V = (D == 1 ? G / 2 : G) / 16;   // uint4 per ring slot
+    constexpr int SLOTS = D == 1 ? 3 : D;
+    uint4 buf[SLOTS][K][V];
+    // loads of G bytes of step `step` into dst (D >= 2), or of line `step`
+    // into the slots h0 (first half) and h1 (second half) (D == 1)
+    auto issue = [&](uint4 (&dst)[K][V], uint32_t step) __attribute__((always_inline)) {
         if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint64_t base = (step < nb[k]) ? body[k] + (uint64_t)G * step : body[0];
+            const uint32_t base = (step < nb[k]) ? body[k] + G * (uint32_t)step : body[0];
 #pragma unroll
-            for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(a.in + base + 16 * v);
+            for (int v = 0; v < V; ++v) dst[k][v] = *(const uint4 *)(cin + base + 16 * v);
         }
         if constexpr (D == 2) __builtin_amdgcn_sched_barrier(0);
     };
+    auto issue_line = [&](uint4 (&h0)[K][V], uint4 (&h1)[K][V], uint32_t line) __attribute__((always_inline)) {
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int d = 0; d < D - 1; ++d)
-        if ((uint64_t)d < maxnb) issue(buf[d], d);
+        for (int k = 0; k < K; ++k) {
+            const uint32_t base = (line < nb[k]) ? body[k] + G * (uint32_t)line : body[0];
+#pragma unroll
+            for (int v = 0; v < V; ++v) h0[k][v] = *(const uint4 *)(cin + base + 16 * v);
+#pragma unroll
+            for (int v = 0; v < V; ++v) h1[k][v] = *(const uint4 *)(cin + base + G / 2 + 16 * v);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    if constexpr (D == 1) {
+        if (maxnb) issue_line(buf[0], buf[1], 0);
+    } else {
+#pragma unroll
+        for (int d = 0; d < D - 1; ++d)
+            if ((uint32_t)d < maxnb) issue(buf[d], d);
+    }
 
     copy16((uint4 *)smem, (const uint4 *)a.img, img / 16, (blockIdx.x * 613u) % (img / 16));
     if (a.mul_lds) copy16((uint4 *)s_mul, (const uint4 *)a.mul, a.mul_lds / 16);
@@ -620,24 +655,25 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
 
     const uint8_t *__restrict__ tab = a.gtab;
     auto cls = [&](uint32_t b) __attribute__((always_inline)) -> uint32_t { return lds_u8(b); };
-    auto row = [&](uint32_t t, uint32_t c) __attribute__((always_inline)) -> uint32_t {
-        return lds_u16(ROWS + ((t + c) << 1));
+    auto row = [&](uint32_t u, uint32_t c2) __attribute__((always_inline)) -> uint32_t {
+        return lds_u16(ROWS + __umul24(u, RB) + c2);
     };
-    // Scalar walk through the global table: from the state (t, cid) over the
-    // classes cl[0 .. nc-1]; returns the new t and sets id to the new state.
-    auto redo = [&](uint32_t t, uint32_t cid, const uint32_t *cl, int nc, uint32_t &id)
+    // Scalar walk through the global table from state s over the doubled
+    // classes c2[b .. nc-1]; returns the new t and sets id to the new state.
+    auto redo = [&](uint64_t s, const uint32_t *c2, int b, int nc, uint32_t &id)
         __attribute__((always_inline)) -> uint32_t {
-        uint64_t s = t == cold ? cid : (uint32_t)(((uint64_t)t * magic) >> 32);
-        for (int i = 0; i < nc; ++i) {
-            const uint64_t at = (s * C + cl[i]) * sizeof(NT);
+        for (int i = b; i < nc; ++i) {
+            const uint64_t at = (s * C + (c2[i] >> 1)) * sizeof(NT);
             const uint32_t w = *(const __attribute__((address_space(4))) uint32_t *)(tab + (at & ~3ull));
             s = (w >> (8 * (uint32_t)(at & 3))) & (uint32_t)(NT)~0u;
         }
         id = (uint32_t)s;
-        return s < H ? (uint32_t)s * C : cold;
+        return s < H ? (uint32_t)s : cold;
     };
-    // Four bytes of every piece (classes c[i][k]): LDS walk, then the pieces
-    // that ended on the cold row walk the word again from its start.
+    // Four bytes of every piece (doubled classes c[i][k]): LDS walk, then the
+    // pieces that ended on the cold row walk the whole word again from its
+    // start (a fixed chain of four scalar loads: measured faster than a
+    // shorter chain of run-time length from the last hot state).
     auto word = [&](uint32_t (&t)[K], uint32_t (&cid)[K], const uint32_t (&c)[4][K]) __attribute__((always_inline)) {
         uint32_t t0[K];
 #pragma unroll
@@ -654,11 +690,13 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
             for (int k = 0; k < K; ++k) {
                 for (uint64_t m = __ballot(t[k] == cold); m; m &= m - 1) {
                     const uint32_t l = (uint32_t)__builtin_ctzll(m);
-                    uint32_t cl[4], id;
+                    uint32_t cl[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) cl[i] = __builtin_amdgcn_readlane(c[i][k], l);
-                    const uint32_t v = redo(__builtin_amdgcn_readlane(t0[k], l), __builtin_amdgcn_readlane(cid[k], l),
-                                            cl, 4, id);
+                    const uint32_t s0 = __builtin_amdgcn_readlane(t0[k], l);
+                    const uint64_t s = s0 == cold ? __builtin_amdgcn_readlane(cid[k], l) : s0;
+                    uint32_t id;
+                    const uint32_t v = redo(s, cl, 0, 4, id);
                     const bool mine = __lane_id() == l;
                     t[k] = mine ? v : t[k];
                     cid[k] = mine ? id : cid[k];
@@ -689,9 +727,10 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                 for (uint64_t m = __ballot(act[k] && nt[k] == cold); m; m &= m - 1) {
                     const uint32_t l = (uint32_t)__builtin_ctzll(m);
                     const uint32_t cl = __builtin_amdgcn_readlane(c[k], l);
+                    const uint32_t sl = __builtin_amdgcn_readlane(st[k], l);
+                    const uint64_t s = sl == cold ? __builtin_amdgcn_readlane(sid[k], l) : sl;
                     uint32_t id;
-                    const uint32_t v = redo(__builtin_amdgcn_readlane(st[k], l), __builtin_amdgcn_readlane(sid[k], l),
-                                            &cl, 1, id);
+                    const uint32_t v = redo(s, &cl, 0, 1, id);
                     const bool mine = __lane_id() == l;
                     nt[k] = mine ? v : nt[k];
                     sid[k] = mine ? id : sid[k];
@@ -710,23 +749,31 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
 #pragma unroll
                     for (int k = 0; k < K; ++k) c[i][k] = cls((word_of(cur[k][w / 4], w % 4) >> (8 * i)) & 255u);
             };
-            auto walk = [&](const uint4 (&cur)[K][V], uint64_t step_no) __attribute__((always_inline)) {
+            auto walk = [&](const uint4 (&cur)[K][V], uint32_t step_no) __attribute__((always_inline)) {
                 uint32_t t[K], id[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) t[k] = st[k], id[k] = sid[k];
-                // the class columns of the next word are read while this word is walked
+                // the class columns of the next word are read while this word
+                // is walked, unless the registers are short (the rolling ring
+                // with four pieces)
+                constexpr bool ahead = !(D == 1 && K >= 4);
                 uint32_t cc[4][K];
                 classes(cc, cur, 0);
 #pragma unroll
                 for (int w = 0; w < 4 * V; ++w) {
-                    uint32_t cn[4][K];
-                    if (w + 1 < 4 * V) classes(cn, cur, w + 1);
-                    word(t, id, cc);
-                    if (w + 1 < 4 * V) {
+                    if constexpr (ahead) {
+                        uint32_t cn[4][K];
+                        if (w + 1 < 4 * V) classes(cn, cur, w + 1);
+                        word(t, id, cc);
+                        if (w + 1 < 4 * V) {
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
+                            for (int i = 0; i < 4; ++i)
 #pragma unroll
-                            for (int k = 0; k < K; ++k) cc[i][k] = cn[i][k];
+                                for (int k = 0; k < K; ++k) cc[i][k] = cn[i][k];
+                        }
+                    } else {
+                        if (w) classes(cc, cur, w);
+                        word(t, id, cc);
                     }
                 }
 #pragma unroll
@@ -736,36 +783,56 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                     sid[k] = in ? id[k] : sid[k];
                 }
             };
-            uint64_t j = 0;
-            for (; j + 2 * D - 1 <= maxnb; j += D) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    issue(buf[(d + D - 1) % D], j + d + D - 1);
-                    walk(buf[d], j + d);
+            uint32_t j = 0;
+            if constexpr (D == 1) {
+                // lines j (slots 0, 1) and j + 1 (slots 0, 2)
+                for (; j + 2 <= maxnb; j += 2) {
+                    walk(buf[0], j);
+                    issue_line(buf[0], buf[2], j + 1);
+                    walk(buf[1], j);
+                    walk(buf[0], j + 1);
+                    if (j + 2 < maxnb) issue_line(buf[0], buf[1], j + 2);
+                    walk(buf[2], j + 1);
                 }
-            }
-            for (; j < maxnb; j += D) {
+                if (j < maxnb) {
+                    walk(buf[0], j);
+                    walk(buf[1], j);
+                }
+            } else {
+                for (; j + 2 * D - 1 <= maxnb; j += D) {
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    if (j + d < maxnb) {
-                        if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
+                    for (int d = 0; d < D; ++d) {
+                        issue(buf[(d + D - 1) % D], j + d + D - 1);
                         walk(buf[d], j + d);
                     }
                 }
-            }
+                for (; j < maxnb; j += D) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) pos[k] += (uint64_t)G * nb[k];
+                    for (int d = 0; d < D; ++d) {
+                        if (j + d < maxnb) {
+                            if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
+                            walk(buf[d], j + d);
+                        }
+                    }
+                }
+            }
         }
-        // tail: fewer than G bytes per piece
+        // tail: fewer than G bytes per piece (the piece bounds are computed
+        // again rather than kept live through the walk)
+        lane_pieces<K, G, TB>(a, c0, c1, pos, end);
+#pragma unroll
+        for (int k = 0; k < K; ++k) pos[k] = c0 + body[k] + (uint64_t)G * nb[k];
         uint32_t maxtail = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
         singles(maxtail);
     }
-    // D-SFA ids of the piece states
+    // D-SFA ids of the piece states; every wave is done with the hot image
+    // before its region takes the ids and the composition scratch
     uint32_t ids[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) ids[k] = st[k] == cold ? sid[k] : (uint32_t)(((uint64_t)st[k] * magic) >> 32);
+    for (int k = 0; k < K; ++k) ids[k] = st[k] == cold ? sid[k] : st[k];
+    __syncthreads();
     if (a.mul_lds) {
         uint32_t x = ids[0];
 #pragma unroll
@@ -806,6 +873,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     X(1, 128, 2, 256) X(2, 128, 2, 256) X(4, 128, 2, 256) \
     X(1, 64, 2, 512) X(2, 64, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
     X(1, 128, 2, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) \
+    X(2, 128, 1, 512) X(3, 128, 1, 512) X(4, 128, 1, 512) \
     X(1, 64, 2, 1024) X(2, 64, 2, 1024) X(1, 128, 2, 1024)
 
 // Once per kernel and device (runtime.hip): checks that the kernel has no

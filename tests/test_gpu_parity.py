@@ -356,6 +356,7 @@ GLOBAL_SHAPES = [(1, 64, 2, 256), (2, 64, 2, 256), (4, 32, 2, 256), (4, 64, 2, 2
                  (1, 128, 2, 256), (2, 128, 2, 256), (4, 128, 2, 256),
                  (1, 64, 2, 512), (2, 64, 2, 512), (4, 32, 2, 512), (4, 64, 2, 512),
                  (1, 128, 2, 512), (2, 128, 2, 512), (2, 128, 3, 512),
+                 (2, 128, 1, 512), (3, 128, 1, 512), (4, 128, 1, 512),
                  (1, 64, 2, 1024), (2, 64, 2, 1024), (1, 128, 2, 1024)]
 
 

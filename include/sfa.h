@@ -64,7 +64,7 @@ typedef enum sfa_status {
     SFA_ERR_UNSUPPORTED_ARCH = 6,  /* current device is not gfx950 */
     SFA_ERR_BUFFER_TOO_SMALL = 7,  /* device buffer or workspace smaller than required */
     SFA_ERR_HIP = 8,               /* a HIP runtime call failed (message has the HIP error) */
-    SFA_ERR_NO_SFA = 9,            /* table has no D-SFA part: use the speculative matcher */
+    SFA_ERR_NO_SFA = 9,            /* no D-SFA the walk can take: use the speculative matcher */
     SFA_ERR_HOST_ALLOC = 10        /* host memory allocation failed */
 } sfa_status;
 
@@ -176,11 +176,16 @@ sfa_status sfa_compiled_desc(const sfa_compiled *c, sfa_table_desc *out);
  *   opts may be NULL (defaults).  force_global = 1 keeps the walk table in
  *   global memory even when it would fit LDS.  A D-SFA whose walk table does
  *   not fit is walked with its most visited rows staged in LDS (as many as
- *   lds_budget holds) and the rest read from global memory; to choose those
- *   rows the loader renumbers the D-SFA states by visit count in a profiling
- *   walk over profile_sample (host bytes like the input) or, without a
- *   sample, over uniformly random byte classes.  Renumbering changes only
- *   internal ids: results are DFA states and never depend on it.
+ *   fill the LDS, or as lds_budget bytes of rows hold; u16 row indices, so
+ *   at most 65,535 rows) and the rest read from global memory; to choose
+ *   those rows the loader renumbers the D-SFA states by visit count in a
+ *   profiling walk over profile_sample (host bytes like the input) or,
+ *   without a sample, over uniformly random byte classes.  Renumbering
+ *   changes only internal ids: results are DFA states and never depend on
+ *   it.  That global-table walk takes at most 128 byte classes; sfa_match
+ *   returns SFA_ERR_NO_SFA for a larger table that does not fit LDS (the
+ *   speculative matcher handles it).  Every device offset of the loader and
+ *   the kernels is 64-bit: walk tables of 4 GiB or more are valid.
  *   Product table: the D-SFA states are closed under reverse composition
  *   (f_u . f_v = f_uv, Lemma 1 in Section 4.3; they form the monoid of
  *   Section 7.1), so for a D-SFA of at most 128
@@ -261,10 +266,11 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  *               words, delta_s applied 2 or 4 times, indexed through a
  *               65,536-entry table of byte-pair classes; available when the
  *               table fits the LDS budget (sfa_table_info.strides).
- *   pieces      K: interleaved pieces each chunk is walked as (1, 2, 4, 8).
+ *   pieces      K: interleaved pieces each chunk is walked as (1, 2, 3, 4, 8).
  *   load_bytes  G: bytes of one piece loaded per step (16, 32, 64, 128).
  *   depth       D: load steps in flight per piece (loads for step j + D - 1
- *               are issued before step j is walked).
+ *               are issued before step j is walked; 1 = the rolling ring of
+ *               the global-table walk described below).
  *   block_threads    TB: threads per block (256, 512, 1024).
  *   lanes_per_chunk  consecutive lanes that share a chunk (power of two
  *               <= 16); the chunk is cut into lanes_per_chunk * K pieces.
@@ -276,11 +282,12 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * 4 KiB it is (1,128,2,512) with lanes_per_chunk raised until the lanes fill
  * one 512-thread block per CU, when ceil(n / n_chunks) is a multiple of
  * 128 * lanes_per_chunk.  Tables in global memory use lanes_per_chunk=1
- * with TB=256: (1,64,2) (2,64,2) (2,64,3) (4,32,2) (4,32,3) (4,32,4) (8,16,2)
- * (8,16,3) (8,16,4) (1,128,2) (2,128,2) (4,64,2); TB=512: (1,64,2) (2,64,2)
- * (2,64,3) (4,32,2) (4,32,3) (4,32,4) (1,128,2) (1,128,3) (1,128,4)
- * (2,128,2) (2,128,3) (4,64,2); TB=1024: (1,64,2) (2,64,2) (1,128,2);
- * default (4,64,2,512).  With
+ * with TB=256: (1,64,2) (2,64,2) (4,32,2) (4,64,2) (1,128,2) (2,128,2)
+ * (4,128,2); TB=512: (1,64,2) (2,64,2) (4,32,2) (4,64,2) (1,128,2) (2,128,2)
+ * (2,128,3) and the rolling rings (2,128,1) (3,128,1) (4,128,1); TB=1024:
+ * (1,64,2) (2,64,2) (1,128,2); default (4,64,2,512).  depth = 1 is a
+ * rolling ring of three half-line slots per piece: every 128-byte line is
+ * requested whole, with 1.5 lines of registers per piece.  With
  * n_chunks = 0 the default chunk count is one block of lanes per CU.
  * Other values give SFA_ERR_INVALID_ARG.  Short chunks lower K first. */
 typedef struct sfa_plan {

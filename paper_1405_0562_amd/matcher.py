@@ -7,6 +7,7 @@ and streams.
 from __future__ import annotations
 
 import ctypes
+from collections import OrderedDict
 from dataclasses import dataclass
 
 import numpy as np
@@ -120,6 +121,8 @@ def _stream_ptr(stream) -> int:
 class Table:
     """A compiled automaton resident in device memory (HBM)."""
 
+    MAX_CALLS = 256   # prepared call shapes kept per table
+
     def __init__(self, compiled: Compiled, device=None, force_global: bool = False, lds_budget: int = 0,
                  renumber: int = 0, profile_sample: np.ndarray | None = None, product: bool = True, stream=None):
         self.compiled = compiled
@@ -132,16 +135,23 @@ class Table:
         nbytes = ctypes.c_size_t()
         check(lib().sfa_table_device_bytes(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(nbytes)))
         with torch.cuda.device(self.device):
-            self.buf = torch.empty(max(256, nbytes.value), dtype=torch.uint8, device=self.device)
+            load_stream = torch.cuda.current_stream() if stream is None else stream
+            with torch.cuda.stream(load_stream):
+                self.buf = torch.empty(max(256, nbytes.value), dtype=torch.uint8, device=self.device)
             h = ctypes.c_void_p()
             check(lib().sfa_load_table(ctypes.byref(desc), ctypes.byref(opts), ctypes.c_void_p(self.buf.data_ptr()),
-                                       nbytes.value, ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+                                       nbytes.value, ctypes.c_void_p(_stream_ptr(load_stream)), ctypes.byref(h)))
             self._h = h
+            # launches on other streams wait for the upload
+            self._uploaded = torch.cuda.Event()
+            self._uploaded.record(load_stream)
+        self._load_stream = _stream_ptr(load_stream)
+        self._synced = {self._load_stream}
         ti = _capi.TableInfo()
         check(lib().sfa_table_get_info(self._h, ctypes.byref(ti)))
         self.info = {f: getattr(ti, f) for f, _ in _capi.TableInfo._fields_}
         self._ws = {}
-        self._calls = {}   # (entry point, n, n_chunks, stream, plan) -> prepared call
+        self._calls = OrderedDict()   # (entry point, n, n_chunks, stream, plan) -> (fn, plan args, bytes)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -156,19 +166,37 @@ class Table:
     def handle(self) -> ctypes.c_void_p:
         return self._h
 
-    def workspace(self, n: int, n_chunks: int, stream=None) -> torch.Tensor:
+    @property
+    def walkable(self) -> bool:
+        """True when sfa_match can walk this table's D-SFA (else only the
+        speculative matcher applies: no D-SFA within the cap, or a global
+        table with more byte classes than the walk takes)."""
+        return self.info["n_sfa"] > 0 and (self.info["table_in_lds"] or self.info["n_classes"] <= 128)
+
+    def _stream_ready(self, stream) -> None:
+        """Makes `stream` wait for the table upload (once per stream)."""
+        sp = _stream_ptr(stream)
+        if sp not in self._synced:
+            (torch.cuda.current_stream() if stream is None else stream).wait_event(self._uploaded)
+            self._synced.add(sp)
+
+    def workspace(self, n: int, n_chunks: int, stream=None, need: int | None = None) -> torch.Tensor:
         """A zero-filled workspace large enough for (n, n_chunks), cached per stream.
 
-        The kernels leave the workspace's control word zero after every call,
-        so a cached workspace is reused without clearing; calls on one stream
-        never overlap.
+        The kernels leave the workspace's control words zero after every
+        call, so a cached workspace is reused without clearing; calls on one
+        stream never overlap.  The workspace is allocated and cleared on the
+        launch stream itself.
         """
-        need = ctypes.c_size_t()
-        check(lib().sfa_match_workspace_bytes(self._h, n, n_chunks, ctypes.byref(need)))
+        if need is None:
+            nb = ctypes.c_size_t()
+            check(lib().sfa_match_workspace_bytes(self._h, n, n_chunks, ctypes.byref(nb)))
+            need = nb.value
         key = _stream_ptr(stream)
         ws = self._ws.get(key)
-        if ws is None or ws.numel() < need.value:
-            ws = torch.zeros(max(need.value, 4096), dtype=torch.uint8, device=self.device)
+        if ws is None or ws.numel() < need:
+            with torch.cuda.stream(torch.cuda.current_stream() if stream is None else stream):
+                ws = torch.zeros(max(need, 4096), dtype=torch.uint8, device=self.device)
             self._ws[key] = ws
         return ws
 
@@ -177,13 +205,14 @@ def load(compiled: Compiled, **kw) -> Table:
     return Table(compiled, **kw)
 
 
-def _prepare(fn_name: str, table: Table, n: int, n_chunks: int, stream, sp: int, plan: dict | None):
-    """Entry point and the arguments that do not change between calls of one shape."""
-    ws = table.workspace(n, n_chunks, stream)
+def _prepare(fn_name: str, table: Table, n: int, n_chunks: int, plan: dict | None):
+    """Entry point, plan arguments and workspace bytes of one call shape."""
+    nb = ctypes.c_size_t()
+    check(lib().sfa_match_workspace_bytes(table.handle, n, n_chunks, ctypes.byref(nb)))
     if plan is None:
-        return getattr(lib(), fn_name), (), ws
+        return getattr(lib(), fn_name), None, nb.value
     p = _capi.Plan(*(int(plan.get(f, 0)) for f, _ in _capi.Plan._fields_))
-    return lib().sfa_match_ex, (ctypes.byref(p), p), ws
+    return lib().sfa_match_ex, p, nb.value
 
 
 def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: torch.Tensor | None, stream,
@@ -197,12 +226,19 @@ def _match(fn_name: str, table: Table, data: torch.Tensor, n_chunks: int, out: t
     key = (fn_name, n, n_chunks, sp, None if plan is None else tuple(sorted(plan.items())))
     call = table._calls.get(key)
     if call is None:
-        call = table._calls[key] = _prepare(fn_name, table, n, n_chunks, stream, sp, plan)
-    fn, extra, ws = call
+        call = table._calls[key] = _prepare(fn_name, table, n, n_chunks, plan)
+        if len(table._calls) > Table.MAX_CALLS:
+            table._calls.popitem(last=False)
+    else:
+        table._calls.move_to_end(key)
+    fn, p, need = call
+    table._stream_ready(stream)
+    ws = table.workspace(n, n_chunks, stream, need)
     if out is None:
-        out = torch.empty(2, dtype=torch.int32, device=table.device)
-    if extra:
-        st = fn(table.handle, data.data_ptr() if n else None, n, n_chunks, extra[0], ws.data_ptr(), ws.numel(),
+        with torch.cuda.stream(torch.cuda.current_stream() if stream is None else stream):
+            out = torch.empty(2, dtype=torch.int32, device=table.device)
+    if p is not None:
+        st = fn(table.handle, data.data_ptr() if n else None, n, n_chunks, ctypes.byref(p), ws.data_ptr(), ws.numel(),
                 out.data_ptr(), sp or None)
     else:
         st = fn(table.handle, data.data_ptr() if n else None, n, n_chunks, ws.data_ptr(), ws.numel(),
@@ -216,8 +252,15 @@ def match(table: Table, data: torch.Tensor, n_chunks: int = 0, out: torch.Tensor
     """Algorithm 5 on the device; returns int32[2] = (final state, accept) on the device.
 
     ``plan`` (optional) is a dict with any of the sfa_plan fields ("stride", "pieces",
-    "load_bytes", "depth", "block_threads", "lanes_per_chunk").
+    "load_bytes", "depth", "block_threads", "lanes_per_chunk").  A table
+    without a walkable D-SFA (none within the state cap, or a global table
+    with more than 128 byte classes) is matched by the speculative kernel
+    (Algorithm 3) instead, with the same result.
     """
+    if not table.walkable:
+        if plan is not None:
+            raise ValueError("a launch plan applies to the D-SFA walk; this table has no walkable D-SFA")
+        return _match("sfa_match_speculative", table, data, n_chunks, out, stream)
     return _match("sfa_match", table, data, n_chunks, out, stream, plan)
 
 

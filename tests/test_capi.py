@@ -78,3 +78,28 @@ def test_null_arguments_are_errors():
     assert L.sfa_match(None, None, 0, 0, None, 0, None, None) == 1
     assert L.sfa_match_speculative(None, None, 0, 0, None, 0, None, None) == 1
     assert L.sfa_load_table(None, None, None, 0, None, ctypes.byref(h)) == 1
+
+
+def test_walk_table_past_4gib_is_planned_with_64_bit_offsets():
+    # A synthetic D-SFA whose transition table holds 2^24 - 1 states x 80
+    # classes of 32-bit ids (5.4 GB): every device offset is 64-bit, so the
+    # planned buffer holds the whole table rather than a wrapped 32-bit size.
+    # Zero-filled arrays (every transition to the identity, one DFA state)
+    # are a valid descriptor and cost no resident memory until written.
+    L = _capi.lib()
+    n_sfa, C = (1 << 24) - 1, 80
+    nxt = np.zeros(n_sfa * C, dtype=np.uint32)
+    mp = np.zeros(n_sfa, dtype=np.uint32)
+    bc = np.zeros(256, dtype=np.uint8)
+    bc[1:C] = np.arange(1, C, dtype=np.uint8)
+    dn = np.zeros(C, dtype=np.uint32)
+    acc = np.zeros(1, dtype=np.uint8)
+    p32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    p8 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    d = _capi.TableDesc(1, 1, n_sfa, C, 0, p8(bc), p32(dn), p8(acc), p32(nxt), p32(mp))
+    nbytes = ctypes.c_size_t()
+    assert L.sfa_table_device_bytes(ctypes.byref(d), None, ctypes.byref(nbytes)) == 0
+    table_bytes = 4 * n_sfa * C
+    assert table_bytes > 1 << 32
+    assert nbytes.value >= table_bytes + n_sfa          # transitions + one mapping entry per state
+    assert nbytes.value < table_bytes + (64 << 20)

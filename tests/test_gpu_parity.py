@@ -123,10 +123,18 @@ def test_c3_over_cap_uses_speculative():
     rx = W.c3_regex(kws)
     data = W.c3_input(6, 1 << 20, kws, rate=1e-5)
     t = gpu_table(rx, False, 1000)
-    assert t.info["n_sfa"] == 0
-    with pytest.raises(sfa.SfaError):
-        run(rx, data, sfa_cap=1000)
+    assert t.info["n_sfa"] == 0 and not t.walkable
+    # match() falls back to the speculative kernel by itself
+    check(rx, data, sfa_cap=1000)
     check(rx, data, speculative=True, sfa_cap=1000)
+    # the C entry point itself reports the missing D-SFA
+    ws = t.workspace(data.size, 0)
+    out = torch.empty(2, dtype=torch.int32, device="cuda")
+    x = to_device(data)
+    assert sfa.lib().sfa_match(t.handle, x.data_ptr(), data.size, 0, ws.data_ptr(), ws.numel(),
+                               out.data_ptr(), None) == 9
+    with pytest.raises(ValueError):
+        sfa.match(t, x, plan=dict(pieces=2))
 
 
 # --------------------------------------------------------------------------

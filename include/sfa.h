@@ -303,6 +303,24 @@ sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint64_t n, uin
                         const sfa_plan *plan, void *d_ws, size_t ws_bytes, sfa_result *d_out,
                         void *stream);
 
+/* sfa_match without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same walk and result as sfa_match with
+ * the default launch plan; d_in and d_out as there.  The workspace is the
+ * library's own: a device array of SFA_NOALLOC_WORKSPACE_BYTES (4 MiB) per
+ * GPU, held until the process ends; the first call on a device takes its
+ * address and clears its control words with a fill kernel on `stream`.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  A call whose plan needs a larger workspace (see
+ * sfa_match_workspace_bytes; e.g. millions of chunks over a large DFA)
+ * returns SFA_ERR_INVALID_ARG before any device work.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from several threads) race and may return wrong results;
+ * serialise them, or use sfa_match with a workspace per stream. */
+#define SFA_NOALLOC_WORKSPACE_BYTES (4u << 20)
+sfa_status sfa_match_noalloc(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
+                             sfa_result *d_out, void *stream);
+
 /* Speculative parallel DFA (Algorithm 3, Section 3): per chunk, every DFA
  * state is simulated as a possible start (|Q| lookups per byte), giving the
  * chunk's mapping T_i; the mappings are composed as in sfa_match.  Works for

@@ -107,6 +107,7 @@ SIGNATURES = {
     "sfa_match_workspace_bytes": (ctypes.c_int, [_P, _U64, _U32, ctypes.POINTER(_SZ)]),
     "sfa_match": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _SZ, _P, _P]),
     "sfa_match_speculative": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _SZ, _P, _P]),
+    "sfa_match_noalloc": (ctypes.c_int, [_P, _P, _U64, _U32, _P, _P]),
     "sfa_match_ex": (ctypes.c_int, [_P, _P, _U64, _U32, ctypes.POINTER(Plan), _P, _SZ, _P, _P]),
     "sfa_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), _U32, _P, _U32, _P, _U32,
                                         ctypes.POINTER(BatchOptions), ctypes.POINTER(_P)]),

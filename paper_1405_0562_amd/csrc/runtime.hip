@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <set>
@@ -921,6 +922,65 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
 extern "C" sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks, void *d_ws,
                                 size_t ws_bytes, sfa_result *d_out, void *stream) {
     return sfa_match_ex(t, d_in, n, n_chunks, nullptr, d_ws, ws_bytes, d_out, stream);
+}
+
+// ---------------------------------------------------------------------------
+// sfa_match_noalloc: sfa_match with the library's own workspace.  The
+// workspace is a file-scope device array (one copy per device, held until
+// the process ends); its address on a device is taken once, with that device
+// current, and the host never passes the array's name to a kernel.
+// ---------------------------------------------------------------------------
+namespace {
+
+static __device__ __align__(256) uint8_t scratch[SFA_NOALLOC_WORKSPACE_BYTES];
+
+__global__ void k_zero_words(uint32_t *p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t *> g_scratch;   // device -> address of scratch on that device
+
+// Address of the device's scratch array; on the first call for a device the
+// control words (the part that must start at zero) are cleared on `stream`
+// with a fill kernel.
+sfa_status device_scratch(int dev, hipStream_t stream, uint8_t **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return SFA_OK;
+    }
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr & 255)) return sfa_fail(SFA_ERR_HIP, "scratch symbol address is not 256-byte aligned");
+    hipLaunchKernelGGL(k_zero_words, dim3(4), dim3(256), 0, stream, (uint32_t *)ptr, (uint32_t)(kWsHeader / 4));
+    HIP_TRY(hipGetLastError());
+    g_scratch[dev] = (uint8_t *)ptr;
+    *out = (uint8_t *)ptr;
+    return SFA_OK;
+}
+
+}  // namespace
+
+extern "C" sfa_status sfa_match_noalloc(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,
+                                        sfa_result *d_out, void *stream) {
+    if (!t) return sfa_fail(SFA_ERR_INVALID_ARG, "null table");
+    if (t->L.n_sfa == 0) return sfa_fail(SFA_ERR_NO_SFA, "table has no D-SFA; use sfa_match_speculative");
+    Plan P;
+    sfa_status st = make_plan(t, n, n_chunks, false, nullptr, P);
+    if (st != SFA_OK) return st;
+    if (P.ws_bytes > SFA_NOALLOC_WORKSPACE_BYTES)
+        return sfa_fail(SFA_ERR_INVALID_ARG, "this call needs " + std::to_string(P.ws_bytes) +
+                                                 " workspace bytes, more than sfa_match_noalloc holds (" +
+                                                 std::to_string((unsigned long long)SFA_NOALLOC_WORKSPACE_BYTES) +
+                                                 "); use sfa_match with a caller workspace");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    uint8_t *ws = nullptr;
+    st = device_scratch(dev, (hipStream_t)stream, &ws);
+    if (st != SFA_OK) return st;
+    return sfa_match_ex(t, d_in, n, n_chunks, nullptr, ws, SFA_NOALLOC_WORKSPACE_BYTES, d_out, stream);
 }
 
 extern "C" sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32_t n_chunks,

@@ -285,10 +285,11 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * with TB=256: (1,64,2) (2,64,2) (4,32,2) (4,64,2) (1,128,2) (2,128,2)
  * (4,128,2); TB=512: (1,64,2) (2,64,2) (4,32,2) (4,64,2) (1,128,2) (2,128,2)
  * (2,128,3) and the rolling rings (2,128,1) (3,128,1) (4,128,1); TB=1024:
- * (1,64,2) (2,64,2) (1,128,2); default (4,64,2,512).  depth = 1 is a
+ * (1,64,2) (2,64,2) (1,128,2); default (4,128,1,512).  depth = 1 is a
  * rolling ring of three half-line slots per piece: every 128-byte line is
  * requested whole, with 1.5 lines of registers per piece.  With
- * n_chunks = 0 the default chunk count is one block of lanes per CU.
+ * n_chunks = 0 the default chunk count is one block of lanes per CU (four
+ * for the global-table walk), with chunks of at least 1 KiB.
  * Other values give SFA_ERR_INVALID_ARG.  Short chunks lower K first. */
 typedef struct sfa_plan {
     uint32_t stride;

@@ -695,7 +695,10 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
     if (n_chunks == 0) {
         const uint64_t target = speculative ? 4096 : 1024;   // bytes per chunk at least
         // default: one block of lanes per CU
-        const uint64_t per_cu = speculative ? kSpecWaves * 8 : global_walk ? kGlobalBlock : kBlock;
+        // (the global-table walk: four blocks per CU, which balances the
+        // CUs' end times better; measured on the 4 GiB keyword workload
+        // 1.99 ms with one block per CU, 1.86 ms with four)
+        const uint64_t per_cu = speculative ? kSpecWaves * 8 : global_walk ? 4 * kGlobalBlock : kBlock;
         const uint64_t max_chunks = (uint64_t)std::max(1u, t->num_cus) * per_cu;
         uint64_t p = std::max<uint64_t>(1, (n + target - 1) / target);
         P.n_chunks = (uint32_t)std::min(p, max_chunks);
@@ -743,13 +746,14 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         if (LPC == 0 || (LPC & (LPC - 1)) || LPC > 16)
             return sfa_fail(SFA_ERR_INVALID_ARG, "plan lanes_per_chunk must be a power of two <= 16");
         if (S == 0) {
-            // global-table walk: default (4, 64, 2) with 512 threads (two
-            // waves per SIMD share the staged rows and hide each other's
-            // LDS latency; 64-byte steps visit each 128-byte line twice,
-            // 32-byte steps four times, with lines evicted in between)
+            // global-table walk: default (4, 128, 1) with 512 threads: two
+            // waves per SIMD share the staged rows and hide each other's LDS
+            // latency, and the rolling ring requests every 128-byte line
+            // whole (64-byte steps read a line in two visits, between which
+            // it leaves the L2: 1.94x the input bytes fetched, against 1.03x)
             if (!user || !user->pieces) K = 4;
-            if (!user || !user->load_bytes) G = 64;
-            if (!user || !user->depth) D = 2;
+            if (!user || !user->load_bytes) G = 128;
+            if (!user || !user->depth) D = 1;
             if (!user || !user->block_threads) TB = kGlobalBlock;
             if (LPC != 1)
                 return sfa_fail(SFA_ERR_INVALID_ARG, "the global-table walk uses one lane per chunk");

@@ -29,8 +29,9 @@ Modules
               NFA run from I, Algorithm 4 over correspondences Q -> P(Q),
               composition of correspondences and Algorithm 5 with
               S_fin = union of f_fin(q) over q in I.
-``scan``      Algorithm 2 in plain C (``seqscan.c``) for large inputs.
-``build``     compiles ``seqscan.c`` with gcc.
+``scan``      Algorithm 2 in plain C (``seqscan.c``) and Algorithm 5 on host
+              threads in plain C (``cpu_sfa.c``) for large inputs.
+``build``     compiles ``seqscan.c`` and ``cpu_sfa.c`` with gcc.
 
 Every function that is not pinned against something other than itself says
 "parity unpinned" in its docstring; the pins live in ``tests/test_oracle_*.py``.

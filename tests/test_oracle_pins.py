@@ -370,3 +370,41 @@ def test_seqscan_c_matches_python_loop():
         assert oscan.scan(d, w) == run_dfa(d, bytes(w))
         for q in range(d.n):
             assert oscan.scan(d, w[:37], q=q) == run_dfa(d, bytes(w[:37]), q)
+
+
+# --------------------------------------------------------------------------
+# cpu_sfa.c (Algorithm 5 on host threads) against Example 1's D-SFA, the
+# Python Algorithm 5 and Algorithm 2
+# --------------------------------------------------------------------------
+def test_cpu_sfa_on_example1():
+    delta, _, _, _ = _example1()
+    s = build_dsfa(delta, 0, np.array([True, False, False]))
+    cls = np.full(256, 1, dtype=np.int64)          # every byte but 'a' acts as b
+    cls[ord("a")] = 0
+    t = oscan.SfaTables(s, cls)
+    word = b"ab" * 7
+    for p in range(1, 17):
+        q, states = oscan.sfa_parallel(t, word, p)
+        ref = sfa_parallel(s, cls, word, p=p)
+        assert states == ref["chunk_states"], p
+        assert q == ref["q_sequential"] == 0, p
+    q, _ = oscan.sfa_parallel(t, word + b"a", 3)
+    assert q == 1                                   # (ab)*a ends in state 1 (Table 1's DFA)
+
+
+@pytest.mark.parametrize("rx", [W.REGEX_C1, W.REGEX_C2, ".*(abc|bcd|cab).*", "(a|b)*a(a|b){2}c?"])
+def test_cpu_sfa_matches_sequential_dfa(rx):
+    d = compile_regex(rx)
+    s, cls = byte_dsfa(d)
+    t = oscan.SfaTables(s, cls)
+    rng = np.random.default_rng(11)
+    alpha = np.frombuffer(b"0123456789abcd", dtype=np.uint8)
+    for n in (0, 1, 5, 97, 4096 + 3, 100_003):
+        w = (W.c1_input(3, n=n - n % 2) if rx == W.REGEX_C1 and n >= 10 else rng.choice(alpha, size=n).astype(np.uint8))
+        want = oscan.scan(d, w)
+        for p in (1, 2, 3, 8, 16, 33, n + 5):
+            q, states = oscan.sfa_parallel(t, w, p)
+            assert q == want, (rx, n, p)
+            if n <= 4096 + 3 and p <= 16:
+                ref = sfa_parallel(s, cls, bytes(w), p=p)
+                assert states == ref["chunk_states"], (rx, n, p)

@@ -645,7 +645,7 @@ def main():
             extra[name] = {k: m[k] for k in ("value", "ms_per_step", "config", "roofline", "result",
                                              "oracle_result", "parity", "speculative")}
     progress("batching")
-    batching = None if args.no_batch else batching_leg(args.seed, args.batch_docs, min(250, args.batch_docs))
+    batching = None if args.no_batch else batching_leg(args.seed, args.batch_docs, args.batch_docs)
     progress("serving")
     serving = None if args.no_serve else serving_leg(args.seed, args.serve_requests)
 

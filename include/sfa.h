@@ -331,7 +331,7 @@ sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64
                                  sfa_result *d_out, void *stream);
 
 /* ------------------------------------------------------------------------
- * Batched matching: many (document, table) jobs in one launch sequence.
+ * Batched matching: many (document, table) jobs in one kernel launch.
  *
  *   Documents are byte ranges of one device buffer, doc d = [doc_off[d],
  *   doc_off[d+1]).  A job (doc, table) is matched exactly as sfa_match would
@@ -340,28 +340,31 @@ sfa_status sfa_match_speculative(const sfa_table *t, const uint8_t *d_in, uint64
  *   d_out[job index].  Every table must have a D-SFA whose stride-1 walk table
  *   is at most 64 KiB (sfa_table_info.strides bit 1).
  *
- *   sfa_batch_create   host planning (pieces, units, groups); doc_off and jobs
- *                      are host arrays, copied into the plan.  tables must stay
- *                      loaded while the plan is used.
+ *   sfa_batch_create   host planning (pieces, work units, work items, the
+ *                      jobs spanning items); doc_off and jobs are host arrays,
+ *                      copied into the plan.  tables must stay loaded while
+ *                      the plan is used.
  *   sfa_batch_workspace_bytes / sfa_batch_upload
  *                      the caller provides a device workspace (256-byte
  *                      aligned) and uploads the plan's descriptors into it once
- *                      (async on stream), together with a contiguous copy of
- *                      the tables' stride-1 walk images when they are staged
- *                      in LDS (taken from the tables' packed host images when
- *                      the batch is created).
- *   sfa_match_batch    launches the walk, group and composition kernels only
- *                      (no allocation, no host synchronisation, no memset),
- *                      so a stream capture of it can be replayed as a graph as
- *                      long as the workspace and table buffers stay in place.
- *                      The document bytes may change between calls.
+ *                      (async on stream), together with the LDS contents (the
+ *                      tables' class columns interleaved, then their stride-1
+ *                      rows) when the tables are staged in LDS (taken from the
+ *                      tables' packed host images when the batch is created).
+ *   sfa_match_batch    enqueues one kernel launch (no allocation, no host
+ *                      synchronisation, no memset), so a stream capture of it
+ *                      can be replayed as a graph as long as the workspace and
+ *                      table buffers stay in place.  The document bytes may
+ *                      change between calls.  Launches of one plan that share
+ *                      a workspace must not overlap (the arrival counters live
+ *                      in it).
  *   sfa_batch_free     frees the host plan.
  * ---------------------------------------------------------------------- */
 typedef struct sfa_batch sfa_batch;
 
 typedef struct sfa_batch_options {
     uint32_t piece_bytes;     /* bytes per piece, multiple of 16 (0 = 4096) */
-    uint32_t group_pieces;    /* pieces per group for jobs longer than that (0 = 32) */
+    uint32_t reserved;        /* must be 0 */
     uint32_t units_per_lane;  /* pieces walked together by one lane: 1, 2 or 4 (0 = 2) */
     uint32_t force_global;    /* 1: read walk tables from global memory instead of LDS */
 } sfa_batch_options;
@@ -370,8 +373,8 @@ typedef struct sfa_batch_info {
     uint32_t n_jobs;
     uint32_t n_docs;          /* documents referenced by at least one job */
     uint64_t n_units;         /* (piece, job) work units */
-    uint64_t n_group_items;   /* (job, group, start state) items of long jobs */
-    uint32_t piece_bytes, group_pieces, units_per_lane, tables_in_lds;
+    uint64_t n_item_map_entries; /* (job, work item, start state) entries of jobs spanning work items */
+    uint32_t piece_bytes, units_per_lane, tables_in_lds, reserved;
     uint64_t workspace_bytes;
 } sfa_batch_info;
 

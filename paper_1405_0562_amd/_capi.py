@@ -71,15 +71,15 @@ class Plan(ctypes.Structure):
 
 
 class BatchOptions(ctypes.Structure):
-    _fields_ = [("piece_bytes", ctypes.c_uint32), ("group_pieces", ctypes.c_uint32),
+    _fields_ = [("piece_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("units_per_lane", ctypes.c_uint32), ("force_global", ctypes.c_uint32)]
 
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("n_jobs", ctypes.c_uint32), ("n_docs", ctypes.c_uint32), ("n_units", ctypes.c_uint64),
-                ("n_group_items", ctypes.c_uint64), ("piece_bytes", ctypes.c_uint32),
-                ("group_pieces", ctypes.c_uint32), ("units_per_lane", ctypes.c_uint32),
-                ("tables_in_lds", ctypes.c_uint32), ("workspace_bytes", ctypes.c_uint64)]
+                ("n_item_map_entries", ctypes.c_uint64), ("piece_bytes", ctypes.c_uint32),
+                ("units_per_lane", ctypes.c_uint32), ("tables_in_lds", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("workspace_bytes", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p

@@ -1,8 +1,8 @@
-"""Batched matching: many (document, table) jobs per launch sequence.
+"""Batched matching: many (document, table) jobs in one persistent launch.
 
 ``Batch`` wraps one host plan (sfa_batch_create) and its device workspace;
-``Batch.run`` only enqueues the batch kernels (sfa_match_batch), so it can be
-captured into a HIP graph (``GraphBatch``) and replayed.  ``Autotuner`` picks
+``Batch.run`` only enqueues the batch kernel (sfa_match_batch, one launch),
+so it can be captured into a HIP graph (``GraphBatch``) and replayed.  ``Autotuner`` picks
 the piece length and pieces per lane for a batch shape by timing candidates
 on the device and caches the choice on disk.
 """
@@ -25,7 +25,6 @@ from .matcher import Table, _stream_ptr
 @dataclass(frozen=True)
 class BatchOptions:
     piece_bytes: int = 0      # 0 = library default (4096)
-    group_pieces: int = 0     # 0 = library default (32)
     units_per_lane: int = 0   # 0 = library default (2)
     force_global: bool = False
 
@@ -49,8 +48,7 @@ class Batch:
         if n_docs < 0:
             raise ValueError("doc_off needs n_docs + 1 entries")
         handles = (ctypes.c_void_p * len(self.tables))(*[t.handle.value for t in self.tables])
-        opts = _capi.BatchOptions(options.piece_bytes, options.group_pieces, options.units_per_lane,
-                                  int(options.force_global))
+        opts = _capi.BatchOptions(options.piece_bytes, 0, options.units_per_lane, int(options.force_global))
         h = ctypes.c_void_p()
         check(lib().sfa_batch_create(handles, len(self.tables), ctypes.c_void_p(self.doc_off.ctypes.data), n_docs,
                                      ctypes.c_void_p(self.jobs.ctypes.data), self.jobs.shape[0],
@@ -94,7 +92,7 @@ class Batch:
 class GraphBatch:
     """A batch captured once into a HIP graph and replayed.
 
-    The graph holds only the batch kernels (no memset, no allocation); the
+    The graph holds only the batch kernel (no memset, no allocation); the
     data tensor is captured by address, so new document bytes are copied into
     ``self.data`` before each replay.
     """
@@ -102,7 +100,7 @@ class GraphBatch:
     def __init__(self, batch: Batch, data: torch.Tensor):
         self.batch = batch
         self.data = data
-        self.graph = torch.cuda.CUDAGraph()
+        self.graph = torch.cuda.CUDAGraph(keep_graph=True)   # the captured graph stays inspectable
         side = torch.cuda.Stream(device=batch.device)
         side.wait_stream(torch.cuda.current_stream(batch.device))
         with torch.cuda.stream(side):
@@ -111,6 +109,7 @@ class GraphBatch:
         torch.cuda.synchronize(batch.device)
         with torch.cuda.graph(self.graph):
             batch.run(self.data)
+        self.graph.instantiate()
 
     def replay(self) -> torch.Tensor:
         self.graph.replay()
@@ -145,12 +144,15 @@ class Autotuner:
     """Times candidate batch options on the device and remembers the best.
 
     Candidates cover the piece length (work per lane, balance between long and
-    short documents) and pieces per lane (ILP vs lane count).  Results are
-    cached in a JSON file keyed by ``shape_key``.
+    short documents), pieces per lane (ILP vs lane count) and the placement
+    of the walk tables (staged in LDS by every block, or read through L1/L2
+    from global memory).  Results are cached in a JSON file keyed by
+    ``shape_key``.
     """
 
     PIECES = (1024, 2048, 4096, 8192, 16384)
     UNITS = (1, 2, 4)
+    PLACEMENTS = (False, True)   # force_global
 
     def __init__(self, cache_path: str | None = None, reps: int = 3):
         self.cache_path = cache_path or os.path.join(os.path.expanduser("~"), ".cache", "paper_1405_0562_amd",
@@ -188,15 +190,16 @@ class Autotuner:
         key = shape_key(tables, doc_off, jobs)
         if key in self.cache and not force:
             c = self.cache[key]
-            return BatchOptions(c["piece_bytes"], 0, c["units_per_lane"]), c
+            return BatchOptions(c["piece_bytes"], c["units_per_lane"], bool(c.get("force_global", False))), c
         trials = []
-        for piece in self.PIECES:
-            for units in self.UNITS:
-                opt = BatchOptions(piece, 0, units)
-                ms = self.time_options(tables, data, doc_off, jobs, opt)
-                trials.append({"piece_bytes": piece, "units_per_lane": units, "ms": ms})
+        for glob in self.PLACEMENTS:
+            for piece in self.PIECES:
+                for units in self.UNITS:
+                    opt = BatchOptions(piece, units, glob)
+                    ms = self.time_options(tables, data, doc_off, jobs, opt)
+                    trials.append({"piece_bytes": piece, "units_per_lane": units, "force_global": glob, "ms": ms})
         best = min(trials, key=lambda t: t["ms"])
         entry = dict(best, trials=trials)
         self.cache[key] = entry
         self._save()
-        return BatchOptions(best["piece_bytes"], 0, best["units_per_lane"]), entry
+        return BatchOptions(best["piece_bytes"], best["units_per_lane"], best["force_global"]), entry

@@ -222,7 +222,7 @@ class GpuBackend:
         self.host_np = self.host_pool.numpy()
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.next_stream = 0
-        self.options = BatchOptions(piece_bytes, 0, units_per_lane)
+        self.options = BatchOptions(piece_bytes, units_per_lane)
         # pinned result slots, reused round robin (more slots than batches in flight)
         self.result_slots = [torch.empty((max_batch_requests, 2), dtype=torch.int32, pin_memory=True)
                              for _ in range(result_slots)]

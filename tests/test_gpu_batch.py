@@ -4,9 +4,11 @@ Each job (document, regex) is checked bit-exactly against the oracle's own
 DFA run over the document (Algorithm 2 in plain C).  Covers all-pairs batches
 of the batching workload at reduced size, random job lists (duplicates, empty
 and unaligned documents, a subset of tables per document), jobs long enough
-to need group composition, tables read from global memory, and graph replay.
+to span work items, tables read from global memory, and graph replay.
 """
 import functools
+
+import ctypes
 
 import numpy as np
 import pytest
@@ -89,16 +91,28 @@ def test_random_jobs_duplicates_empty_and_unaligned_docs():
         assert np.array_equal(got, oracle_jobs(regexes, data, off, jobs))
 
 
-def test_long_jobs_use_group_composition():
+def test_jobs_spanning_work_items():
+    """Jobs whose pieces lie in several work items: per-item mappings and one
+    arrival per item, with pieces less than an item apart (few jobs per
+    document) and more than an item apart (more jobs per document than units
+    per item)."""
     regexes = W.c4_regexes(2)[:4]
-    lens = np.array([1, 100, 70_000, 300_000, 5, 131_072], dtype=np.int64)
+    lens = np.array([1, 100, 70_000, 300_000, 5, 131_072, 0, 4099], dtype=np.int64)
     off = np.zeros(len(lens) + 1, dtype=np.int64)
     np.cumsum(lens, out=off[1:])
     data = W.uniform_over(W.rng_for(9, 7), W.ALPHABET_C4, int(off[-1]))
-    jobs = np.array([(d, t) for d in range(len(lens)) for t in range(4)], dtype=np.uint32)
-    got, b = run_batch(regexes, data, off, jobs, piece_bytes=128, group_pieces=8)
-    assert b.info["n_group_items"] > 0
-    assert np.array_equal(got, oracle_jobs(regexes, data, off, jobs))
+    x = torch.from_numpy(data).cuda()
+    few = np.array([(d, t) for d in range(len(lens)) for t in range(4)], dtype=np.uint32)
+    many = np.array([(d, j % 4) for d in range(len(lens)) for j in range(70)], dtype=np.uint32)
+    for jobs in (few, many):
+        want = oracle_jobs(regexes, data, off, jobs)
+        for units in (1, 2, 4):
+            got, b = run_batch(regexes, data, off, jobs, piece_bytes=128, units_per_lane=units)
+            assert b.info["n_item_map_entries"] > 0
+            assert np.array_equal(got, want), (jobs.shape, units)
+            # the arrival counters reset themselves: the same workspace serves again
+            for _ in range(3):
+                assert np.array_equal(b.run(x).cpu().numpy(), want)
 
 
 def test_global_tables_and_c1_c2_regexes():
@@ -127,6 +141,27 @@ def test_batch_matches_single_stream_path():
         assert single == got[i].tolist()
 
 
+def graph_node_types(graph):
+    """Node types of a captured graph (0 = kernel), through the HIP runtime."""
+    hip = ctypes.CDLL("libamdhip64.so")
+    raw = graph.raw_cuda_graph()
+    if not isinstance(raw, int):   # a capsule around the pointer
+        get = ctypes.pythonapi.PyCapsule_GetPointer
+        get.restype, get.argtypes = ctypes.c_void_p, [ctypes.py_object, ctypes.c_char_p]
+        raw = get(raw, None)
+    g = ctypes.c_void_p(raw)
+    n = ctypes.c_size_t(0)
+    assert hip.hipGraphGetNodes(g, None, ctypes.byref(n)) == 0
+    nodes = (ctypes.c_void_p * n.value)()
+    assert hip.hipGraphGetNodes(g, nodes, ctypes.byref(n)) == 0
+    types = []
+    for nd in nodes:
+        t = ctypes.c_int(-1)
+        assert hip.hipGraphNodeGetType(ctypes.c_void_p(nd), ctypes.byref(t)) == 0
+        types.append(t.value)
+    return types
+
+
 def test_graph_replay_with_new_data():
     regexes = W.c4_regexes(4)
     data, off = small_docs(8, 100)
@@ -135,6 +170,7 @@ def test_graph_replay_with_new_data():
     b = sfa.Batch(tabs, off, jobs)
     x = torch.from_numpy(data).cuda()
     g = sfa.GraphBatch(b, x)
+    assert graph_node_types(g.graph) == [0]      # one node, a kernel: the whole batch is one launch
     for rep in range(3):
         new = W.uniform_over(W.rng_for(100 + rep, 7), W.ALPHABET_C4, data.size)
         g.data.copy_(torch.from_numpy(new))
@@ -155,8 +191,9 @@ def test_autotuner_picks_a_valid_option(tmp_path):
     x = torch.from_numpy(data).cuda()
     tuner = sfa.Autotuner(cache_path=str(tmp_path / "tune.json"), reps=1)
     opt, entry = tuner.tune(tabs, x, off, jobs)
-    assert opt.piece_bytes in sfa.Autotuner.PIECES and len(entry["trials"]) == 15
+    assert opt.piece_bytes in sfa.Autotuner.PIECES and len(entry["trials"]) == 30
+    assert {t["force_global"] for t in entry["trials"]} == {False, True}   # LDS and L2 placement both timed
     b = sfa.Batch(tabs, off, jobs, opt)
     assert np.array_equal(b.run(x).cpu().numpy(), oracle_jobs(regexes, data, off, jobs))
     opt2, _ = sfa.Autotuner(cache_path=str(tmp_path / "tune.json")).tune(tabs, x, off, jobs)
-    assert opt2.piece_bytes == opt.piece_bytes
+    assert opt2 == opt

@@ -17,6 +17,7 @@ sample and checks every GPU result over all the bytes.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -434,6 +435,9 @@ def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0)):
         reqs = W.c5_requests(seed, n_req=n_req, qps=qps)
         arrivals = [(r.arrival_s, r.table, r.data) for r in reqs]
         srv = Server(backend, pool_bytes=1 << 30, max_inflight=3, big_bytes=8 << 20)
+        # no collector pauses inside either timed loop
+        gc.collect()
+        gc.disable()
         run_open_loop(srv, arrivals)
         st = srv.latency_stats()
         served = {r.rid: r.result for r in srv.finished}
@@ -448,6 +452,7 @@ def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0)):
             lat.append(time.perf_counter() - t0 - at)
             equal = equal and served.get(i) == res
         span = time.perf_counter() - t0
+        gc.enable()
         lat = np.array(lat)
         total = sum(int(a[2].size) for a in arrivals)
         points.append({"load_x_plain_saturation": mult, "qps": qps,

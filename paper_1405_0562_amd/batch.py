@@ -36,7 +36,8 @@ class Batch:
     ``run``; ``jobs`` is an (n_jobs, 2) array of (document, table index).
     """
 
-    def __init__(self, tables: list[Table], doc_off, jobs, options: BatchOptions = BatchOptions(), stream=None):
+    def __init__(self, tables: list[Table], doc_off, jobs, options: BatchOptions = BatchOptions(), stream=None,
+                 ws: torch.Tensor | None = None, out: torch.Tensor | None = None):
         if not tables:
             raise ValueError("at least one table is required")
         self.tables = list(tables)
@@ -57,9 +58,18 @@ class Batch:
         info = _capi.BatchInfo()
         check(lib().sfa_batch_get_info(self._h, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in _capi.BatchInfo._fields_}
+        # a caller's workspace and output buffers are used when they are large
+        # enough (a server keeps them per stream, so no launch allocates)
+        need = max(256, self.info["workspace_bytes"])
         with torch.cuda.device(self.device):
-            self.ws = torch.empty(max(256, self.info["workspace_bytes"]), dtype=torch.uint8, device=self.device)
-            self.out = torch.empty((self.jobs.shape[0], 2), dtype=torch.int32, device=self.device)
+            if ws is not None and ws.dtype == torch.uint8 and ws.numel() >= need and ws.data_ptr() % 256 == 0:
+                self.ws = ws
+            else:
+                self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            if out is not None and out.dtype == torch.int32 and out.shape[0] >= self.jobs.shape[0]:
+                self.out = out[:self.jobs.shape[0]]
+            else:
+                self.out = torch.empty((self.jobs.shape[0], 2), dtype=torch.int32, device=self.device)
             check(lib().sfa_batch_upload(self._h, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                          ctypes.c_void_p(_stream_ptr(stream))))
 

@@ -210,7 +210,7 @@ class GpuBackend:
 
     def __init__(self, tables, pool_bytes: int = 1 << 30, n_streams: int = 3, piece_bytes: int = 4096,
                  units_per_lane: int = 2, device=None, max_batch_requests: int = 4096, result_slots: int = 64,
-                 warmup: bool = True):
+                 ws_bytes: int = 32 << 20, warmup: bool = True, warmup_max_bytes: int = 64 << 20):
         import torch
         from .batch import Batch, BatchOptions
         self.torch = torch
@@ -227,28 +227,42 @@ class GpuBackend:
         self.result_slots = [torch.empty((max_batch_requests, 2), dtype=torch.int32, pin_memory=True)
                              for _ in range(result_slots)]
         self.next_slot = 0
+        # batch workspace and output per stream: launches on one stream run
+        # in order, so they share them, and serving allocates nothing
+        self.max_batch_requests = max_batch_requests
+        self.warmup_max_bytes = warmup_max_bytes
+        self.stream_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=self.device) for _ in self.streams]
+        self.stream_out = [torch.empty((max_batch_requests, 2), dtype=torch.int32, device=self.device)
+                           for _ in self.streams]
         if warmup:
             self.warmup()
 
     def warmup(self) -> None:
-        """Run the launch paths once on every stream before serving: a small
-        and a 1 MiB single-stream match (different kernel shapes) and a
-        two-request batch.  First launches load kernel code and set up
-        streams, which would otherwise land on the first requests served."""
+        """Run the launch paths before serving: every table alone at sizes
+        from 4 KiB to the largest request the pool holds (the matcher picks
+        different kernels and workspaces by size) and a batch over all tables
+        on every stream.  First launches load kernel code, set kernel
+        attributes and grow the allocator's cache, which would otherwise land
+        on the first requests served."""
+        cap = min(self.dev_pool.numel(), self.warmup_max_bytes)
+        sizes = [4096, 1 << 20]
+        while sizes[-1] * 8 <= cap:
+            sizes.append(sizes[-1] * 8)
+        blanks = [np.zeros(n, dtype=np.uint8) for n in sizes]
+        for t in range(len(self.tables)):
+            for x in blanks:
+                self.launch_single(Request(-1, t, x, 0.0), 0)[0].synchronize()
         small = np.zeros(4096, dtype=np.uint8)
-        big = np.zeros(1 << 20, dtype=np.uint8)
         for _ in self.streams:
-            handles = [self.launch_single(Request(-1, 0, small, 0.0), 0),
-                       self.launch_single(Request(-1, 0, big, 0.0), 1 << 16),
-                       self.launch_batch([Request(-1, 0, small, 0.0), Request(-1, len(self.tables) - 1, small, 0.0)],
-                                         (1 << 16) + (1 << 20))]
-            for h in handles:
-                h[0].synchronize()
+            reqs = [Request(-1, t, small, 0.0) for t in range(len(self.tables))]
+            h = self.launch_batch(reqs, 0)
+            h[0].synchronize()
+        self.torch.cuda.synchronize(self.device)
 
     def _stream(self):
-        s = self.streams[self.next_stream % len(self.streams)]
+        i = self.next_stream % len(self.streams)
         self.next_stream += 1
-        return s
+        return i, self.streams[i]
 
     def _stage(self, requests, off, stream):
         cur = off
@@ -270,14 +284,17 @@ class GpuBackend:
         torch = self.torch
         if len(requests) == 1:
             return self.launch_single(requests[0], off)
-        s = self._stream()
+        i, s = self._stream()
         total = self._stage(requests, off, s)
         lens = np.array([r.nbytes for r in requests], dtype=np.int64)
         doc_off = np.zeros(len(requests) + 1, dtype=np.int64)
         np.cumsum(lens, out=doc_off[1:])
         jobs = np.stack([np.arange(len(requests)), [r.table for r in requests]], axis=1).astype(np.uint32)
         with torch.cuda.stream(s):
-            b = self.Batch(self.tables, doc_off, jobs, self.options, stream=s)
+            b = self.Batch(self.tables, doc_off, jobs, self.options, stream=s, ws=self.stream_ws[i],
+                           out=self.stream_out[i])
+            if b.ws is not self.stream_ws[i]:
+                self.stream_ws[i] = b.ws   # grown once for a larger plan, kept for the next ones
             data = self.dev_pool[off:off + max(total, 1)]
             out = b.run(data, stream=s)
             host_out = self._slot(len(requests))
@@ -289,7 +306,7 @@ class GpuBackend:
     def launch_single(self, request, off):
         torch = self.torch
         from .matcher import match
-        s = self._stream()
+        _, s = self._stream()
         self._stage([request], off, s)
         with torch.cuda.stream(s):
             data = self.dev_pool[off:off + request.nbytes]

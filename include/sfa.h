@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define SFA_ABI_VERSION 1u
+#define SFA_ABI_VERSION 2u
 
 typedef enum sfa_status {
     SFA_OK = 0,
@@ -104,12 +104,38 @@ typedef struct sfa_compile_info {
     uint32_t sfa_over_cap; /* 1 if the D-SFA construction stopped at the cap */
     double   dfa_seconds;  /* host time of parse + NFA + DFA + minimisation */
     double   sfa_seconds;  /* host time of the D-SFA construction */
+    uint32_t sfa_lazy;     /* 1: the D-SFA was built on the fly (sfa_compiled_build_lazy) */
+    uint32_t reserved;
 } sfa_compile_info;
 
 sfa_status sfa_compile(const char *pattern, size_t pattern_len, uint32_t sfa_cap,
                        uint32_t dfa_cap, sfa_compiled **out);
 sfa_status sfa_compiled_info(const sfa_compiled *c, sfa_compile_info *out);
 void       sfa_compiled_free(sfa_compiled *c);
+
+/* On-the-fly D-SFA (Section 5.1, the remark that on-the-fly construction
+ * carries over from the subset construction to the correspondence
+ * construction): for a D-SFA compilation without a D-SFA (over its cap, or
+ * sfa_cap 0), build only the states that walks over sample reach.  The
+ * sample is walked in runs of walk_bytes starting every start_every bytes,
+ * each from the identity, the way the matchers start every piece; a
+ * transition a run takes for the first time is constructed then (state
+ * f' = f followed by the DFA transition, looked up among the states built so
+ * far), and at max_states states (identity included) construction stops
+ * and a run that needs a new state ends there.  Transitions that no run took
+ * stay unbuilt: SFA_UNBUILT in the descriptor's sfa_next.  The partial D-SFA
+ * replaces the compilation's empty one (info.n_sfa = states built,
+ * info.sfa_lazy = 1) and is loaded like a complete one (sfa_load_table).
+ * The matchers walk it with the global-table walk: a piece that reaches an
+ * unbuilt transition stops at its last built state f and position p, and its
+ * mapping is f followed, for every start state, by the DFA over the rest of
+ * the piece from p (Algorithm 3 for that piece); it composes like any other.
+ *   Limits: max_states in [1, 16777214]; start_every, walk_bytes >= 1.
+ *   SFA_ERR_INVALID_ARG for an N-SFA compilation or one that already has a
+ *   complete D-SFA; calling it again rebuilds from the new sample. */
+#define SFA_UNBUILT 0xFFFFFFFFu
+sfa_status sfa_compiled_build_lazy(sfa_compiled *c, const uint8_t *sample, uint64_t sample_bytes,
+                                   uint32_t start_every, uint32_t walk_bytes, uint32_t max_states);
 
 /* N-SFA compilation: the SFA of Definition 3 built from the regex's position
  * automaton (Glushkov; state 0 initial, states 1.. the byte-set leaves in
@@ -144,7 +170,9 @@ sfa_status sfa_compiled_nsfa_sets(const sfa_compiled *c, sfa_nsfa_sets *out);
  *   byte_class[256]             class id (< n_classes) of each byte value
  *   dfa_next[n_dfa*n_classes]   delta(q, c) at [q*n_classes + c]
  *   dfa_accept[n_dfa]           0/1
- *   sfa_next[n_sfa*n_classes]   delta_s(f, c); state 0 must be the identity
+ *   sfa_next[n_sfa*n_classes]   delta_s(f, c); state 0 must be the identity;
+ *                               SFA_UNBUILT marks a transition of a partial
+ *                               (on-the-fly) D-SFA that was not constructed
  *   sfa_map[n_sfa*n_dfa]        f(q) at [f*n_dfa + q]
  * n_sfa == 0 means no D-SFA (sfa_next, sfa_map may be NULL).
  * Limits: n_dfa <= 65535, n_sfa <= 16777215, 1 <= n_classes <= 256, q0 < n_dfa. */
@@ -184,7 +212,12 @@ sfa_status sfa_compiled_desc(const sfa_compiled *c, sfa_table_desc *out);
  *   changes only internal ids: results are DFA states and never depend on
  *   it.  That global-table walk takes at most 128 byte classes; sfa_match
  *   returns SFA_ERR_NO_SFA for a larger table that does not fit LDS (the
- *   speculative matcher handles it).  Every device offset of the loader and
+ *   speculative matcher handles it).  A partial D-SFA (some SFA_UNBUILT
+ *   transitions) is always walked that way, without the product table: an
+ *   unbuilt transition reads as a reserved id in the global table and as a
+ *   parking row in the hot image, and the piece finishes as described at
+ *   sfa_compiled_build_lazy (the workspace then also holds one 16-byte record
+ *   per piece).  Every device offset of the loader and
  *   the kernels is 64-bit: walk tables of 4 GiB or more are valid.
  *   Product table: the D-SFA states are closed under reverse composition
  *   (f_u . f_v = f_uv, Lemma 1 in Section 4.3; they form the monoid of
@@ -219,6 +252,8 @@ typedef struct sfa_table_info {
     uint32_t strides;        /* bit s set: stride-s LDS walk tables are present (s = 1, 2, 4) */
     uint32_t product_table;  /* 1: compositions reduce D-SFA ids through the product table */
     uint64_t device_bytes;   /* bytes used in d_buf */
+    uint32_t partial;        /* 1: some D-SFA transitions are unbuilt (on-the-fly D-SFA) */
+    uint32_t reserved;
 } sfa_table_info;
 
 sfa_status sfa_table_device_bytes(const sfa_table_desc *desc, const sfa_load_options *opts,

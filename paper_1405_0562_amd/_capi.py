@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsfa.so")
 
-SFA_ABI_VERSION = 1
+SFA_ABI_VERSION = 2
 
 STATUS = {
     0: "SFA_OK", 1: "SFA_ERR_INVALID_ARG", 2: "SFA_ERR_PARSE", 3: "SFA_ERR_DFA_TOO_LARGE",
@@ -33,7 +33,8 @@ class ParseError(SfaError, ValueError):
 class CompileInfo(ctypes.Structure):
     _fields_ = [("n_dfa", ctypes.c_uint32), ("n_sfa", ctypes.c_uint32), ("n_classes", ctypes.c_uint32),
                 ("q0", ctypes.c_uint32), ("n_positions", ctypes.c_uint32), ("sfa_over_cap", ctypes.c_uint32),
-                ("dfa_seconds", ctypes.c_double), ("sfa_seconds", ctypes.c_double)]
+                ("dfa_seconds", ctypes.c_double), ("sfa_seconds", ctypes.c_double),
+                ("sfa_lazy", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class TableDesc(ctypes.Structure):
@@ -62,7 +63,7 @@ class TableInfo(ctypes.Structure):
                 ("q0", ctypes.c_uint32), ("next_bytes", ctypes.c_uint32), ("map_bytes", ctypes.c_uint32),
                 ("table_in_lds", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
                 ("strides", ctypes.c_uint32), ("product_table", ctypes.c_uint32),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("partial", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Plan(ctypes.Structure):
@@ -98,6 +99,7 @@ SIGNATURES = {
     "sfa_compiled_nsfa_sets": (ctypes.c_int, [_P, ctypes.POINTER(NsfaSets)]),
     "sfa_compiled_free": (None, [_P]),
     "sfa_compiled_desc": (ctypes.c_int, [_P, ctypes.POINTER(TableDesc)]),
+    "sfa_compiled_build_lazy": (ctypes.c_int, [_P, _P, _U64, _U32, _U32, _U32]),
     "sfa_table_device_bytes": (ctypes.c_int, [ctypes.POINTER(TableDesc), ctypes.POINTER(LoadOptions),
                                               ctypes.POINTER(_SZ)]),
     "sfa_load_table": (ctypes.c_int, [ctypes.POINTER(TableDesc), ctypes.POINTER(LoadOptions), _P, _SZ, _P,

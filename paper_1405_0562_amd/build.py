@@ -20,7 +20,7 @@ HOST_SOURCES = ["compiler.cpp"]
 HIP_SOURCES = [
     "runtime.hip", "batch.hip", "stream.hip",
     "walk_lds_s1.hip", "walk_lds_s2.hip", "walk_lds_s4.hip",
-    "walk_global_u8.hip", "walk_global_u16.hip", "walk_global_u32.hip",
+    "walk_global_u8.hip", "walk_global_u16.hip", "walk_global_u32.hip", "walk_partial.hip",
 ]
 BUILD_DIR = os.path.join(HERE, "_build")
 HIP_FLAGS = [

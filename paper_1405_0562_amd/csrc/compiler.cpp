@@ -937,6 +937,66 @@ extern "C" sfa_status sfa_compile_nsfa(const char *pattern, size_t pattern_len, 
     return SFA_OK;
 }
 
+// On-the-fly D-SFA: runs over the sample from the identity, constructing a
+// transition the first time a run takes it (the correspondence construction
+// of Algorithm 4 driven by the text instead of a worklist).
+extern "C" sfa_status sfa_compiled_build_lazy(sfa_compiled *c, const uint8_t *sample, uint64_t sample_bytes,
+                                              uint32_t start_every, uint32_t walk_bytes, uint32_t max_states) {
+    if (!c || (sample_bytes && !sample)) return sfa_fail(SFA_ERR_INVALID_ARG, "null argument");
+    if (c->nsfa) return sfa_fail(SFA_ERR_INVALID_ARG, "on-the-fly construction takes a D-SFA compilation");
+    if (c->n_sfa && !c->lazy) return sfa_fail(SFA_ERR_INVALID_ARG, "the compilation already has a complete D-SFA");
+    if (start_every == 0 || walk_bytes == 0 || max_states == 0 || max_states > 16777214u)
+        return sfa_fail(SFA_ERR_INVALID_ARG, "start_every, walk_bytes and max_states must be positive "
+                                             "(max_states at most 16777214)");
+    try {
+        Timer t_sfa;
+        const uint32_t n = c->n_dfa, C = c->n_classes;
+        std::vector<std::vector<uint16_t>> cols(C, std::vector<uint16_t>(n));
+        for (uint32_t f = 0; f < C; ++f)
+            for (uint32_t q = 0; q < n; ++q) cols[f][q] = (uint16_t)c->dfa_next[(size_t)q * C + f];
+        std::vector<uint16_t> rows;
+        for (uint32_t q = 0; q < n; ++q) rows.push_back((uint16_t)q);
+        RowTable tab(rows, n);
+        size_t slot;
+        tab.find(rows.data(), RowTable::hash(rows.data(), n), slot);
+        tab.insert_at(slot, 0, 1);
+        std::vector<uint32_t> snext(C, SFA_UNBUILT);
+        std::vector<uint16_t> tmp(n);
+        uint32_t m = 1;
+        for (uint64_t s0 = 0; s0 < sample_bytes; s0 += start_every) {
+            const uint64_t s1 = std::min<uint64_t>(sample_bytes, s0 + walk_bytes);
+            uint32_t f = 0;
+            for (uint64_t i = s0; i < s1; ++i) {
+                const uint32_t k = c->byte_class[sample[i]];
+                uint32_t t = snext[(size_t)f * C + k];
+                if (t == SFA_UNBUILT) {
+                    const uint16_t *row = &rows[(size_t)f * n];
+                    const uint16_t *col = cols[k].data();
+                    for (uint32_t q = 0; q < n; ++q) tmp[q] = col[row[q]];
+                    t = tab.find(tmp.data(), RowTable::hash(tmp.data(), n), slot);
+                    if (t == UINT32_MAX) {
+                        if (m >= max_states) break;   // no room: this run ends here
+                        t = m++;
+                        rows.insert(rows.end(), tmp.begin(), tmp.end());
+                        snext.insert(snext.end(), C, SFA_UNBUILT);
+                        tab.insert_at(slot, t, m);
+                    }
+                    snext[(size_t)f * C + k] = t;
+                }
+                f = t;
+            }
+        }
+        c->n_sfa = m;
+        c->lazy = 1;
+        c->sfa_next.swap(snext);
+        c->sfa_map.assign(rows.begin(), rows.end());
+        c->sfa_seconds = t_sfa.seconds();
+    } catch (const std::bad_alloc &) {
+        return sfa_fail(SFA_ERR_HOST_ALLOC, "out of host memory");
+    }
+    return SFA_OK;
+}
+
 extern "C" sfa_status sfa_compiled_nsfa_sets(const sfa_compiled *c, sfa_nsfa_sets *out) {
     if (!c || !out) return sfa_fail(SFA_ERR_INVALID_ARG, "null argument");
     if (!c->nsfa) return sfa_fail(SFA_ERR_INVALID_ARG, "not an N-SFA compilation");
@@ -957,6 +1017,8 @@ extern "C" sfa_status sfa_compiled_info(const sfa_compiled *c, sfa_compile_info 
     out->sfa_over_cap = c->over_cap;
     out->dfa_seconds = c->dfa_seconds;
     out->sfa_seconds = c->sfa_seconds;
+    out->sfa_lazy = c->lazy;
+    out->reserved = 0;
     return SFA_OK;
 }
 

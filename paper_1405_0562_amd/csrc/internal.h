@@ -11,7 +11,7 @@
 // classes and, when built, its D-SFA.
 struct sfa_compiled {
     uint32_t n_dfa = 0, n_sfa = 0, n_classes = 0, q0 = 0;
-    uint32_t n_positions = 0, over_cap = 0;
+    uint32_t n_positions = 0, over_cap = 0, lazy = 0;
     double dfa_seconds = 0, sfa_seconds = 0;
     uint8_t byte_class[256] = {};
     std::vector<uint32_t> dfa_next;   // [n_dfa * n_classes]
@@ -64,6 +64,7 @@ struct Layout {
     uint64_t off_himg = 0;   // global-table walk: hot image (u8 classes[256], (hot_rows + 1) x C u16 entries)
     uint32_t himg_bytes = 0;
     uint32_t renumbered = 0; // 1: D-SFA ids were renumbered by visit count
+    uint32_t partial = 0;    // 1: on-the-fly D-SFA with unbuilt transitions (largest id of next_w)
 };
 
 inline int stride_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : -1; }

@@ -116,7 +116,8 @@ sfa_status validate(const sfa_table_desc *d) {
         if (!d->sfa_next || !d->sfa_map) return sfa_fail(SFA_ERR_INVALID_ARG, "null D-SFA array");
         const uint64_t ns = (uint64_t)d->n_sfa * d->n_classes;
         for (uint64_t i = 0; i < ns; ++i)
-            if (d->sfa_next[i] >= d->n_sfa) return sfa_fail(SFA_ERR_INVALID_ARG, "sfa_next out of range");
+            if (d->sfa_next[i] >= d->n_sfa && d->sfa_next[i] != SFA_UNBUILT)
+                return sfa_fail(SFA_ERR_INVALID_ARG, "sfa_next out of range");
         const uint64_t nm = (uint64_t)d->n_sfa * d->n_dfa;
         for (uint64_t i = 0; i < nm; ++i)
             if (d->sfa_map[i] >= d->n_dfa) return sfa_fail(SFA_ERR_INVALID_ARG, "sfa_map out of range");
@@ -124,6 +125,14 @@ sfa_status validate(const sfa_table_desc *d) {
             if (d->sfa_map[q] != q) return sfa_fail(SFA_ERR_INVALID_ARG, "D-SFA state 0 is not the identity");
     }
     return SFA_OK;
+}
+
+// True when some transition of d's D-SFA is unbuilt (an on-the-fly D-SFA).
+bool is_partial(const sfa_table_desc *d) {
+    const uint64_t ns = (uint64_t)d->n_sfa * d->n_classes;
+    for (uint64_t i = 0; i < ns; ++i)
+        if (d->sfa_next[i] == SFA_UNBUILT) return true;
+    return false;
 }
 
 uint64_t ipow(uint64_t b, uint32_t e) {
@@ -138,7 +147,7 @@ uint64_t ipow(uint64_t b, uint32_t e) {
 // that state ids compose like the mappings they stand for (Lemma 1).
 bool product_defined(const sfa_table_desc *d) {
     const uint32_t m = d->n_sfa, C = d->n_classes, n = d->n_dfa;
-    if (m == 0 || (uint64_t)m * C * n > (1u << 24)) return false;
+    if (m == 0 || (uint64_t)m * C * n > (1u << 24) || is_partial(d)) return false;
     std::vector<uint8_t> seen(m, 0);
     std::vector<uint32_t> order{0};
     seen[0] = 1;
@@ -170,7 +179,11 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
     L.n_sfa = d->n_sfa;
     L.C = d->n_classes;
     L.q0 = d->q0;
-    L.next_w = d->n_sfa <= 256 ? 1 : d->n_sfa <= 65536 ? 2 : 4;
+    L.partial = d->n_sfa && is_partial(d) ? 1 : 0;
+    // a partial D-SFA keeps the largest id of the entry width for unbuilt
+    // transitions
+    const uint64_t ids = (uint64_t)d->n_sfa + L.partial;
+    L.next_w = ids <= 256 ? 1 : ids <= 65536 ? 2 : 4;
     L.map_w = d->n_dfa <= 256 ? 1 : 2;
     uint64_t off = 0;
     L.off_cls = off;
@@ -193,7 +206,7 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
         off = align256(off + L.mul_bytes);
     }
     const uint32_t extra = kWalkExtraLds + ((L.mul_bytes + 15) & ~15u);
-    const bool allow_lds = d->n_sfa && !(o && o->force_global);
+    const bool allow_lds = d->n_sfa && !L.partial && !(o && o->force_global);
     const uint64_t budget = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : kDefaultLdsBudget + kPairTable,
                                                lds_limit > extra ? lds_limit - extra : 0);
     for (uint32_t S : {1u, 2u, 4u}) {
@@ -217,18 +230,20 @@ Layout plan(const sfa_table_desc *d, const sfa_load_options *o, uint32_t lds_lim
     const bool any_img = L.img[0].present || L.img[1].present || L.img[2].present;
     if (d->n_sfa && !any_img && L.C <= kGlobalMaxClasses) {
         // global-table walk: a hot image of as many leading rows as the LDS
-        // (or the caller's budget for the rows) holds, plus the cold row.
-        // After the walk the piece ids and the composition scratch reuse the
-        // image's region, so only the product table and the flag word are
-        // kept apart.  Entries are row indices in u16.
+        // (or the caller's budget for the rows) holds, plus the cold row (and
+        // for a partial D-SFA the parking row after it).  After the walk the
+        // piece ids and the composition scratch reuse the image's region, so
+        // only the product table and the flag word are kept apart.  Entries
+        // are row indices in u16.
         const uint64_t rb = 2ull * L.C;
-        const uint64_t keep = ((L.mul_bytes + 15) & ~15u) + 16 + 256 + rb;
+        const uint64_t extra_rows = 1 + L.partial;
+        const uint64_t keep = ((L.mul_bytes + 15) & ~15u) + 16 + 256 + extra_rows * rb;
         const uint64_t room = lds_limit > keep ? lds_limit - keep : 0;
         const uint64_t hb = std::min<uint64_t>((o && o->lds_budget) ? o->lds_budget : room, room);
-        const uint64_t h = std::min<uint64_t>({(uint64_t)d->n_sfa, hb / rb, 65535});
+        const uint64_t h = std::min<uint64_t>({(uint64_t)d->n_sfa, hb / rb, 65536 - extra_rows});
         L.hot_rows = (uint32_t)h;
         L.off_himg = off;
-        L.himg_bytes = (uint32_t)(256 + (h + 1) * rb);
+        L.himg_bytes = (uint32_t)(256 + (h + extra_rows) * rb);
         off = align256(off + L.himg_bytes);
     }
     L.total = off;
@@ -262,6 +277,7 @@ std::vector<uint32_t> trap_states(const sfa_table_desc *d) {
             auto &[v, c] = call.back();
             if (c < C) {
                 const uint32_t w = d->sfa_next[(uint64_t)v * C + c++];
+                if (w == SFA_UNBUILT) continue;
                 if (index[w] == none) {
                     index[w] = low[w] = next_index++;
                     stack.push_back(w);
@@ -285,8 +301,10 @@ std::vector<uint32_t> trap_states(const sfa_table_desc *d) {
             bool closed = comp.size() <= kTrapScc;
             for (uint32_t q : comp) on[q] = 2;      // 2: in the component being tested
             for (size_t i = 0; closed && i < comp.size(); ++i)
-                for (uint32_t cc = 0; cc < C; ++cc)
-                    if (on[d->sfa_next[(uint64_t)comp[i] * C + cc]] != 2) { closed = false; break; }
+                for (uint32_t cc = 0; cc < C; ++cc) {
+                    const uint32_t w = d->sfa_next[(uint64_t)comp[i] * C + cc];
+                    if (w == SFA_UNBUILT || on[w] != 2) { closed = false; break; }
+                }
             for (uint32_t q : comp) on[q] = 0;
             if (closed && out.size() + comp.size() <= kTrapTotal) out.insert(out.end(), comp.begin(), comp.end());
         }
@@ -310,6 +328,7 @@ std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_option
             const uint64_t b0 = (uint64_t)w * part, b1 = std::min<uint64_t>(o->profile_bytes, b0 + part);
             for (uint64_t i = b0; i < b1; ++i) {
                 s = d->sfa_next[(uint64_t)s * C + d->byte_class[o->profile_sample[i]]];
+                if (s == SFA_UNBUILT) s = 0;   // unbuilt: the walker starts over
                 ++count[s];
             }
         }
@@ -322,6 +341,7 @@ std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_option
                 x ^= x >> 17;
                 x ^= x << 5;
                 s = d->sfa_next[(uint64_t)s * C + (x % C)];
+                if (s == SFA_UNBUILT) s = 0;
                 ++count[s];
             }
         }
@@ -356,7 +376,10 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
         rmap.resize((uint64_t)m * n);
         for (uint32_t s = 0; s < m; ++s) {
             const uint32_t t = perm[s];
-            for (uint32_t c = 0; c < C; ++c) rnext[(uint64_t)t * C + c] = perm[d0->sfa_next[(uint64_t)s * C + c]];
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t u = d0->sfa_next[(uint64_t)s * C + c];
+                rnext[(uint64_t)t * C + c] = u == SFA_UNBUILT ? u : perm[u];
+            }
             std::memcpy(&rmap[(uint64_t)t * n], &d0->sfa_map[(uint64_t)s * n], sizeof(uint32_t) * n);
         }
         dd.sfa_next = rnext.data();
@@ -371,7 +394,7 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
     for (uint64_t i = 0; i < (uint64_t)d->n_dfa * C; ++i)
         put<uint16_t>(img, L.off_dnext, i, (uint16_t)d->dfa_next[i]);
     for (uint64_t i = 0; i < (uint64_t)d->n_sfa * C; ++i) {
-        uint32_t v = d->sfa_next[i];
+        uint32_t v = d->sfa_next[i];   // SFA_UNBUILT becomes the largest id of the width
         if (L.next_w == 1) put<uint8_t>(img, L.off_next, i, (uint8_t)v);
         else if (L.next_w == 2) put<uint16_t>(img, L.off_next, i, (uint16_t)v);
         else put<uint32_t>(img, L.off_next, i, v);
@@ -409,14 +432,16 @@ void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, 
     if (L.himg_bytes) {
         // hot image of the global-table walk: doubled class indices (the
         // column byte offsets), then rows 0..H-1 and the cold row H, entries
-        // u (u < H) or H
-        const uint32_t H = L.hot_rows;
+        // u (u < H) or H; a partial D-SFA adds the parking row H + 1, whose
+        // entries are H + 1, and its unbuilt entries in rows < H are H (the
+        // scalar walk through the global table finds them unbuilt there)
+        const uint32_t H = L.hot_rows, last = H + L.partial;
         for (int b = 0; b < 256; ++b) img[L.off_himg + b] = (uint8_t)(2 * d->byte_class[b]);
         const uint64_t rows = L.off_himg + 256;
-        for (uint32_t r = 0; r <= H; ++r)
+        for (uint32_t r = 0; r <= last; ++r)
             for (uint32_t c = 0; c < C; ++c) {
-                const uint32_t u = r < H ? d->sfa_next[(uint64_t)r * C + c] : H;
-                put<uint16_t>(img, rows, (uint64_t)r * C + c, (uint16_t)std::min(u, H));
+                const uint32_t u = r < H ? d->sfa_next[(uint64_t)r * C + c] : r;
+                put<uint16_t>(img, rows, (uint64_t)r * C + c, (uint16_t)(r < H ? std::min(u, H) : u));
             }
     }
     for (uint32_t S : {1u, 2u, 4u}) {
@@ -514,6 +539,7 @@ extern "C" sfa_status sfa_table_get_info(const sfa_table *t, sfa_table_info *out
     out->strides = (t->L.img[0].present ? 2u : 0u) | (t->L.img[1].present ? 4u : 0u) | (t->L.img[2].present ? 16u : 0u);
     out->product_table = t->L.mul_bytes ? 1u : 0u;
     out->device_bytes = t->L.total;
+    out->partial = t->L.partial;
     return SFA_OK;
 }
 
@@ -587,8 +613,12 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
 }
 
 
-bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
+bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, bool partial) {
 #define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
+    if (partial) {
+        SFA_PARTIAL_SHAPES(SFA_SHAPE_OK)
+        return false;
+    }
     SFA_GLOBAL_SHAPES(SFA_SHAPE_OK)
 #undef SFA_SHAPE_OK
     return false;
@@ -608,6 +638,7 @@ struct Plan {
     uint32_t stage_bytes = 0;   // LDS at offset 0 the finishing blocks may use for staging
     uint32_t map_stride = 0, super_blocks = 0, n_super = 1, groups1 = 1, final_groups = 1, stage1 = 0, stage2 = 0;
     size_t ws_maps = 0, ws_groups = 0, ws_bytes = 0;   // workspace offsets and size
+    size_t ws_park = 0;         // partial D-SFA: park records (one per piece), after the rest
 };
 
 // Groups for a composition of E elements: about sqrt(E) groups, so that the
@@ -757,7 +788,7 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
             if (!user || !user->block_threads) TB = kGlobalBlock;
             if (LPC != 1)
                 return sfa_fail(SFA_ERR_INVALID_ARG, "the global-table walk uses one lane per chunk");
-            if (!global_shape_ok(K, G, D, TB))
+            if (!global_shape_ok(K, G, D, TB, t->L.partial))
                 return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth) not supported by the global walk");
         } else if (!lds_shape_ok(K, G, D, TB)) {
             return sfa_fail(SFA_ERR_INVALID_ARG, "plan (pieces, load_bytes, depth, block_threads) not supported");
@@ -766,13 +797,13 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         // short chunks: fewer pieces, then fewer lanes per chunk
         while (K > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) {
             K /= 2;
-            if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB)) {
+            if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB, t->L.partial)) {
                 G = 64;
                 D = 2;
             }
         }
         while (LPC > 1 && P.chunk_len < (uint64_t)LPC * K * G * 2) LPC /= 2;
-        if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB))
+        if (S ? !lds_shape_ok(K, G, D, TB) : !global_shape_ok(K, G, D, TB, t->L.partial))
             return sfa_fail(SFA_ERR_INVALID_ARG, "no launch shape for this plan");
         // every piece of a full chunk is whole G-byte load groups when L is a
         // multiple of LPC * K * G (no byte-at-a-time tail); used when that
@@ -793,6 +824,10 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
     }
     P.stage_bytes = stage_bytes(t, P, speculative);
     plan_grid(P, t->L.n_dfa, !speculative && t->L.mul_bytes);
+    if (!speculative && t->L.partial) {
+        P.ws_park = align256(P.ws_bytes);
+        P.ws_bytes = P.ws_park + (size_t)P.blocks * P.K * P.TB * sizeof(ParkRec);
+    }
     return SFA_OK;
 }
 
@@ -860,6 +895,10 @@ extern "C" sfa_status sfa_match_workspace_bytes(const sfa_table *t, uint64_t n, 
         const uint64_t B = ((uint64_t)a.n_chunks * 16 + 255) / 256;
         const uint64_t ms = ((uint64_t)t->L.n_dfa + 7) & ~7ull;
         bound = std::max<size_t>(bound, kWsHeader + align256(B * ms * 2) + B * ms * 2);
+        // partial D-SFA (global-table walk, one lane per chunk): park records
+        // for blocks of up to 1024 lanes and 4 pieces per lane
+        if (t->L.partial)
+            bound = align256(bound) + (((uint64_t)a.n_chunks + 1024) / 256 + 1) * 256 * 4 * sizeof(ParkRec);
     }
     *out_bytes = std::max(a.ws_bytes, bound);
     return SFA_OK;
@@ -906,6 +945,12 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.img = t->d_base + t->L.off_himg;
         a.img_bytes = t->L.himg_bytes;
         a.gtab = t->d_base + t->L.off_next;
+        if (t->L.partial) {
+            a.partial = 1;
+            a.park = (ParkRec *)((uint8_t *)d_ws + P.ws_park);
+            a.dnext = (const uint16_t *)(t->d_base + t->L.off_dnext);
+            a.cls = (const uint16_t *)(t->d_base + t->L.off_dcls);
+        }
         a.n_classes = t->L.C;
         a.hot_rows = t->L.hot_rows;
         a.cold = t->L.hot_rows;
@@ -915,9 +960,17 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.map_lds = a.map_bytes <= a.region_bytes;
         const size_t lds = (size_t)g.region + a.mul_lds + 16;
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
-        if (t->L.next_w == 1) e = dispatch_global<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
-        else if (t->L.next_w == 2) e = dispatch_global<uint16_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
-        else e = dispatch_global<uint32_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        if (t->L.partial) {
+            if (t->L.next_w == 1) e = dispatch_partial<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            else if (t->L.next_w == 2) e = dispatch_partial<uint16_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            else e = dispatch_partial<uint32_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        } else if (t->L.next_w == 1) {
+            e = dispatch_global<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        } else if (t->L.next_w == 2) {
+            e = dispatch_global<uint16_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        } else {
+            e = dispatch_global<uint32_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        }
     }
     if (e != hipSuccess) return sfa_fail(SFA_ERR_HIP, std::string("walk launch: ") + hipGetErrorString(e));
     return SFA_OK;

@@ -102,7 +102,39 @@ struct MatchArgs {
     uint32_t *block_ids;     // product mode: [gridDim.x] block products
     uint32_t *run_ids;       // product mode: [n_super] run products
     sfa_result *out;
+    // partial (on-the-fly) D-SFA, global-table walk: a piece that reaches an
+    // unbuilt transition parks on row cold + 1 and leaves a ParkRec
+    uint32_t partial;
+    struct ParkRec *park;    // [gridDim.x * K * TB], piece e of block b at b * K * TB + e
+    const uint16_t *dnext;   // DFA transitions u16 [n_dfa * C] (class offsets in cls)
 };
+
+// A parked piece: it reached an unbuilt D-SFA transition at byte pos, in
+// D-SFA state `state` (built); its bytes run to end.
+struct ParkRec {
+    uint64_t pos, end;
+    uint32_t state, pad;
+};
+
+// piece id of a parked piece among the block's piece ids
+constexpr uint32_t kParkedId = 0xFFFFFFFFu;
+
+// The mapping of parked piece e (of this block, E pieces per block) applied
+// to x: x through the mapping of the state the piece stopped in (`map_at`),
+// then through the DFA over the rest of the piece (the speculative walk of
+// Algorithm 3, for the one start state x).
+template <typename MapAt>
+__device__ __forceinline__ uint32_t parked_apply(const MatchArgs &a, MapAt map_at, uint32_t E, uint32_t e, uint32_t x) {
+    const ParkRec *r = a.park + (size_t)blockIdx.x * E + e;
+    const uint64_t pos = __hip_atomic_load(&r->pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t end = __hip_atomic_load(&r->end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t st = __hip_atomic_load(&r->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t y = map_at(st, x);
+    const uint8_t *dn = (const uint8_t *)a.dnext;
+    const uint32_t rb = 2 * a.n_classes;
+    for (uint64_t i = pos; i < end; ++i) y = *(const uint16_t *)(dn + y * rb + a.cls[a.in[i]]);
+    return y;
+}
 
 // Phase 1 of a composition: the elements 0..E-1 (mappings, in text order) are
 // cut into G groups of R consecutive elements; for every (group g, start
@@ -142,7 +174,7 @@ __device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, u
 // s_ids) become the block mapping M[q], written to out_map (u16).  The
 // mapping rows are read from LDS (copied over the walk-table region) when
 // they fit.
-template <typename MT>
+template <typename MT, bool PARTIAL = false>
 __device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem, const uint32_t *s_ids, uint32_t E,
                               uint32_t *scratch, uint16_t *__restrict__ out_map) {
     const uint32_t n = a.n_dfa, G = a.groups, R = E / G;
@@ -151,7 +183,13 @@ __device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem,
         copy16((uint4 *)smem, (const uint4 *)a.map, (a.map_bytes + 15) / 16);
         __syncthreads();
         const MT *m = (const MT *)smem;
-        auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[s_ids[e] * n + x]; };
+        auto map_at = [&](uint32_t id, uint32_t x) -> uint32_t { return m[id * n + x]; };
+        auto get = [&](uint32_t e, uint32_t x) -> uint32_t {
+            const uint32_t id = s_ids[e];
+            if constexpr (PARTIAL)
+                if (id == kParkedId) return parked_apply(a, map_at, E, e, x);
+            return map_at(id, x);
+        };
         if (G == 1) {
             follow_groups(get, E, R, 1, n, out_map);
             return;
@@ -159,7 +197,13 @@ __device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem,
         follow_groups(get, E, R, G, n, target);
     } else {
         const MT *__restrict__ m = (const MT *)a.map;
-        auto get = [&](uint32_t e, uint32_t x) -> uint32_t { return m[(size_t)s_ids[e] * n + x]; };
+        auto map_at = [&](uint32_t id, uint32_t x) -> uint32_t { return m[(size_t)id * n + x]; };
+        auto get = [&](uint32_t e, uint32_t x) -> uint32_t {
+            const uint32_t id = s_ids[e];
+            if constexpr (PARTIAL)
+                if (id == kParkedId) return parked_apply(a, map_at, E, e, x);
+            return map_at(id, x);
+        };
         if (G == 1) {
             follow_groups(get, E, R, 1, n, out_map);
             return;
@@ -582,7 +626,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 // its walk, the piece ids and the composition scratch take the end of that
 // region ([region_bytes, R)) and [0, region_bytes) is free for staging;
 // [R, R + mul_lds) the product table (product mode); then the flag word.
-template <int K, int G, int D, typename NT, int TB>
+template <int K, int G, int D, typename NT, int TB, bool PARTIAL>
 __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr uint32_t ROWS = 256;                          // rows follow the class table
@@ -592,6 +636,11 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     uint32_t *s_scr = s_ids + K * TB;
     uint32_t *s_flag = (uint32_t *)(smem + a.mul_off + a.mul_lds);
     const uint32_t C = a.n_classes, H = a.hot_rows, cold = a.cold, RB = 2 * C;
+    // partial D-SFA: a piece parks on row cold + 1 (its entries lead back to
+    // it) once the scalar walk finds an unbuilt transition; never reached
+    // otherwise (hot entries are at most cold)
+    const uint32_t parked = cold + 1;
+    constexpr uint32_t kUnbuilt = (uint32_t)(NT)~0u;
 
     uint64_t c0, c1, pos[K], end[K];
     lane_pieces<K, G, TB>(a, c0, c1, pos, end);
@@ -660,21 +709,38 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     };
     // Scalar walk through the global table from state s over the doubled
     // classes c2[b .. nc-1]; returns the new t and sets id to the new state.
-    auto redo = [&](uint64_t s, const uint32_t *c2, int b, int nc, uint32_t &id)
+    // At an unbuilt transition (partial D-SFA) it stops: returns the parking
+    // row, id = the state before byte `at`, the byte's index.
+    auto redo = [&](uint64_t s, const uint32_t *c2, int b, int nc, uint32_t &id, int &at_byte)
         __attribute__((always_inline)) -> uint32_t {
         for (int i = b; i < nc; ++i) {
             const uint64_t at = (s * C + (c2[i] >> 1)) * sizeof(NT);
             const uint32_t w = *(const __attribute__((address_space(4))) uint32_t *)(tab + (at & ~3ull));
-            s = (w >> (8 * (uint32_t)(at & 3))) & (uint32_t)(NT)~0u;
+            const uint32_t u = (w >> (8 * (uint32_t)(at & 3))) & kUnbuilt;
+            if constexpr (PARTIAL) {
+                if (u == kUnbuilt) {
+                    id = (uint32_t)s;
+                    at_byte = i;
+                    return parked;
+                }
+            }
+            s = u;
         }
         id = (uint32_t)s;
         return s < H ? (uint32_t)s : cold;
+    };
+    // park record of this lane's piece k: the byte at pos, in state id
+    auto park_at = [&](int k, uint64_t pos, uint32_t id) __attribute__((always_inline)) {
+        ParkRec *r = a.park + ((size_t)blockIdx.x * TB + threadIdx.x) * K + k;
+        r->pos = pos;
+        r->state = id;
     };
     // Four bytes of every piece (doubled classes c[i][k]): LDS walk, then the
     // pieces that ended on the cold row walk the whole word again from its
     // start (a fixed chain of four scalar loads: measured faster than a
     // shorter chain of run-time length from the last hot state).
-    auto word = [&](uint32_t (&t)[K], uint32_t (&cid)[K], const uint32_t (&c)[4][K]) __attribute__((always_inline)) {
+    auto word = [&](uint32_t (&t)[K], uint32_t (&cid)[K], const uint32_t (&c)[4][K], uint32_t boff)
+        __attribute__((always_inline)) {
         uint32_t t0[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) t0[k] = t[k];
@@ -696,8 +762,11 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                     const uint32_t s0 = __builtin_amdgcn_readlane(t0[k], l);
                     const uint64_t s = s0 == cold ? __builtin_amdgcn_readlane(cid[k], l) : s0;
                     uint32_t id;
-                    const uint32_t v = redo(s, cl, 0, 4, id);
+                    int at = 0;
+                    const uint32_t v = redo(s, cl, 0, 4, id, at);
                     const bool mine = __lane_id() == l;
+                    if constexpr (PARTIAL)
+                        if (v == parked && mine) park_at(k, (uint64_t)(cin - a.in) + body[k] + boff + (uint32_t)at, id);
                     t[k] = mine ? v : t[k];
                     cid[k] = mine ? id : cid[k];
                 }
@@ -730,8 +799,11 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                     const uint32_t sl = __builtin_amdgcn_readlane(st[k], l);
                     const uint64_t s = sl == cold ? __builtin_amdgcn_readlane(sid[k], l) : sl;
                     uint32_t id;
-                    const uint32_t v = redo(s, &cl, 0, 1, id);
+                    int at = 0;
+                    const uint32_t v = redo(s, &cl, 0, 1, id, at);
                     const bool mine = __lane_id() == l;
+                    if constexpr (PARTIAL)
+                        if (v == parked && mine) park_at(k, pos[k], id);
                     nt[k] = mine ? v : nt[k];
                     sid[k] = mine ? id : sid[k];
                 }
@@ -749,7 +821,8 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
 #pragma unroll
                     for (int k = 0; k < K; ++k) c[i][k] = cls((word_of(cur[k][w / 4], w % 4) >> (8 * i)) & 255u);
             };
-            auto walk = [&](const uint4 (&cur)[K][V], uint32_t step_no) __attribute__((always_inline)) {
+            // cur holds bytes [boff, boff + 16 V) of every piece's body
+            auto walk = [&](const uint4 (&cur)[K][V], uint32_t step_no, uint32_t boff) __attribute__((always_inline)) {
                 uint32_t t[K], id[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) t[k] = st[k], id[k] = sid[k];
@@ -764,7 +837,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                     if constexpr (ahead) {
                         uint32_t cn[4][K];
                         if (w + 1 < 4 * V) classes(cn, cur, w + 1);
-                        word(t, id, cc);
+                        word(t, id, cc, boff + 4 * w);
                         if (w + 1 < 4 * V) {
 #pragma unroll
                             for (int i = 0; i < 4; ++i)
@@ -773,7 +846,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                         }
                     } else {
                         if (w) classes(cc, cur, w);
-                        word(t, id, cc);
+                        word(t, id, cc, boff + 4 * w);
                     }
                 }
 #pragma unroll
@@ -787,23 +860,23 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
             if constexpr (D == 1) {
                 // lines j (slots 0, 1) and j + 1 (slots 0, 2)
                 for (; j + 2 <= maxnb; j += 2) {
-                    walk(buf[0], j);
+                    walk(buf[0], j, G * j);
                     issue_line(buf[0], buf[2], j + 1);
-                    walk(buf[1], j);
-                    walk(buf[0], j + 1);
+                    walk(buf[1], j, G * j + G / 2);
+                    walk(buf[0], j + 1, G * (j + 1));
                     if (j + 2 < maxnb) issue_line(buf[0], buf[1], j + 2);
-                    walk(buf[2], j + 1);
+                    walk(buf[2], j + 1, G * (j + 1) + G / 2);
                 }
                 if (j < maxnb) {
-                    walk(buf[0], j);
-                    walk(buf[1], j);
+                    walk(buf[0], j, G * j);
+                    walk(buf[1], j, G * j + G / 2);
                 }
             } else {
                 for (; j + 2 * D - 1 <= maxnb; j += D) {
 #pragma unroll
                     for (int d = 0; d < D; ++d) {
                         issue(buf[(d + D - 1) % D], j + d + D - 1);
-                        walk(buf[d], j + d);
+                        walk(buf[d], j + d, G * (j + d));
                     }
                 }
                 for (; j < maxnb; j += D) {
@@ -811,7 +884,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                     for (int d = 0; d < D; ++d) {
                         if (j + d < maxnb) {
                             if (j + d + D - 1 < maxnb) issue(buf[(d + D - 1) % D], j + d + D - 1);
-                            walk(buf[d], j + d);
+                            walk(buf[d], j + d, G * (j + d));
                         }
                     }
                 }
@@ -827,11 +900,20 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
         for (int k = 0; k < K; ++k) maxtail = max(maxtail, (uint32_t)(end[k] - pos[k]));
         singles(maxtail);
     }
-    // D-SFA ids of the piece states; every wave is done with the hot image
+    // D-SFA ids of the piece states (a parked piece: kParkedId, its record
+    // completed with the piece's end); every wave is done with the hot image
     // before its region takes the ids and the composition scratch
     uint32_t ids[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) ids[k] = st[k] == cold ? sid[k] : st[k];
+    for (int k = 0; k < K; ++k) {
+        ids[k] = st[k] == cold ? sid[k] : st[k];
+        if constexpr (PARTIAL) {
+            if (st[k] == parked) {
+                ids[k] = kParkedId;
+                a.park[((size_t)blockIdx.x * TB + threadIdx.x) * K + k].end = end[k];
+            }
+        }
+    }
     __syncthreads();
     if (a.mul_lds) {
         uint32_t x = ids[0];
@@ -846,9 +928,9 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     const uint32_t E = K * TB;
     uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
     if (a.n_dfa <= 256)
-        compose_block<uint8_t>(a, smem, s_ids, E, s_scr, bmap);
+        compose_block<uint8_t, PARTIAL>(a, smem, s_ids, E, s_scr, bmap);
     else
-        compose_block<uint16_t>(a, smem, s_ids, E, s_scr, bmap);
+        compose_block<uint16_t, PARTIAL>(a, smem, s_ids, E, s_scr, bmap);
     block_done(a, smem, s_scr, s_flag);
 }
 
@@ -875,6 +957,10 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     X(1, 128, 2, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) \
     X(2, 128, 1, 512) X(3, 128, 1, 512) X(4, 128, 1, 512) \
     X(1, 64, 2, 1024) X(2, 64, 2, 1024) X(1, 128, 2, 1024)
+
+// Shapes of the global-table walk for a partial (on-the-fly) D-SFA: the
+// default plan and the shapes it falls back to for short chunks.
+#define SFA_PARTIAL_SHAPES(X) X(4, 128, 1, 512) X(2, 128, 1, 512) X(1, 64, 2, 512)
 
 // Once per kernel and device (runtime.hip): checks that the kernel has no
 // static LDS (its dynamic LDS starts at address 0, which lds_u8/lds_u16
@@ -909,8 +995,20 @@ template <typename NT>
 hipError_t dispatch_global(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
                            hipStream_t s, const MatchArgs &a) {
 #define SFA_SHAPE_LAUNCH(k, g, d, tb) \
-    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb>, blocks, tb, lds, s, a);
+    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb, false>, blocks, tb, lds, s, a);
     SFA_GLOBAL_SHAPES(SFA_SHAPE_LAUNCH)
+#undef SFA_SHAPE_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+// The same for a partial D-SFA (SFA_PARTIAL_SHAPES), instantiated for the
+// three id widths in walk_partial.hip.
+template <typename NT>
+hipError_t dispatch_partial(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
+                            hipStream_t s, const MatchArgs &a) {
+#define SFA_SHAPE_LAUNCH(k, g, d, tb) \
+    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb, true>, blocks, tb, lds, s, a);
+    SFA_PARTIAL_SHAPES(SFA_SHAPE_LAUNCH)
 #undef SFA_SHAPE_LAUNCH
     return hipErrorInvalidValue;
 }
@@ -927,5 +1025,11 @@ extern SFA_DISPATCH_SHAPE(4);
 extern SFA_DISPATCH_GLOBAL(uint8_t);
 extern SFA_DISPATCH_GLOBAL(uint16_t);
 extern SFA_DISPATCH_GLOBAL(uint32_t);
+#define SFA_DISPATCH_PARTIAL(NT) \
+    template hipError_t dispatch_partial<NT>(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, size_t, hipStream_t, \
+                                             const MatchArgs &)
+extern SFA_DISPATCH_PARTIAL(uint8_t);
+extern SFA_DISPATCH_PARTIAL(uint16_t);
+extern SFA_DISPATCH_PARTIAL(uint32_t);
 
 }  // namespace sfa_rt

@@ -29,6 +29,7 @@ class CompileInfo:
     sfa_over_cap: bool
     dfa_seconds: float
     sfa_seconds: float
+    sfa_lazy: bool = False
 
 
 class Compiled:
@@ -44,10 +45,26 @@ class Compiled:
         check(entry(raw, len(raw), sfa_cap, dfa_cap, ctypes.byref(h)))
         self._h = h
         self._sets = None
+        self._refresh_info()
+
+    def _refresh_info(self):
         ci = _capi.CompileInfo()
         check(lib().sfa_compiled_info(self._h, ctypes.byref(ci)))
         self.info = CompileInfo(ci.n_dfa, ci.n_sfa, ci.n_classes, ci.q0, ci.n_positions,
-                                bool(ci.sfa_over_cap), ci.dfa_seconds, ci.sfa_seconds)
+                                bool(ci.sfa_over_cap), ci.dfa_seconds, ci.sfa_seconds, bool(ci.sfa_lazy))
+
+    def build_lazy(self, sample, start_every: int = 256, walk_bytes: int = 4096,
+                   max_states: int = DEFAULT_SFA_CAP) -> "Compiled":
+        """On-the-fly D-SFA for a compilation without one: only the states that
+        runs over ``sample`` (walk_bytes each, one every start_every bytes,
+        from the identity) reach are built; the rest stay unbuilt and pieces
+        that reach them finish through the DFA.  Returns self."""
+        x = np.ascontiguousarray(np.frombuffer(sample, dtype=np.uint8) if isinstance(sample, (bytes, bytearray))
+                                 else np.asarray(sample, dtype=np.uint8))
+        check(lib().sfa_compiled_build_lazy(self._h, ctypes.c_void_p(x.ctypes.data if x.size else 0), x.size,
+                                            start_every, walk_bytes, max_states))
+        self._refresh_info()
+        return self
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_status_strings_and_version():
     L = _capi.lib()
-    assert L.sfa_abi_version() == 1
+    assert L.sfa_abi_version() == _capi.SFA_ABI_VERSION == 2
     for s in range(11):
         assert L.sfa_status_string(s)
 
@@ -56,17 +56,17 @@ def test_loader_validation_without_gpu():
     arr = c.arrays()
     nxt = np.ascontiguousarray(arr["sfa_next"].astype(np.uint32).ravel())
     nxt[3] = 99
-    bad = _capi.TableDesc(1, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
+    bad = _capi.TableDesc(_capi.SFA_ABI_VERSION, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
                           nxt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), d.sfa_map)
     assert L.sfa_table_device_bytes(ctypes.byref(bad), None, ctypes.byref(nbytes)) == 1
     # state 0 must be the identity
     mp = np.ascontiguousarray(arr["sfa_map"].astype(np.uint32).ravel())
     mp[0], mp[1] = mp[1], mp[0]
-    bad2 = _capi.TableDesc(1, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
+    bad2 = _capi.TableDesc(_capi.SFA_ABI_VERSION, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
                            d.sfa_next, mp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
     assert L.sfa_table_device_bytes(ctypes.byref(bad2), None, ctypes.byref(nbytes)) == 1
     assert b"identity" in L.sfa_last_error()
-    bad3 = _capi.TableDesc(2, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
+    bad3 = _capi.TableDesc(_capi.SFA_ABI_VERSION + 1, d.n_dfa, d.n_sfa, d.n_classes, d.q0, d.byte_class, d.dfa_next, d.dfa_accept,
                            d.sfa_next, d.sfa_map)
     assert L.sfa_table_device_bytes(ctypes.byref(bad3), None, ctypes.byref(nbytes)) == 1
 
@@ -96,7 +96,7 @@ def test_walk_table_past_4gib_is_planned_with_64_bit_offsets():
     acc = np.zeros(1, dtype=np.uint8)
     p32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
     p8 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-    d = _capi.TableDesc(1, 1, n_sfa, C, 0, p8(bc), p32(dn), p8(acc), p32(nxt), p32(mp))
+    d = _capi.TableDesc(_capi.SFA_ABI_VERSION, 1, n_sfa, C, 0, p8(bc), p32(dn), p8(acc), p32(nxt), p32(mp))
     nbytes = ctypes.c_size_t()
     assert L.sfa_table_device_bytes(ctypes.byref(d), None, ctypes.byref(nbytes)) == 0
     table_bytes = 4 * n_sfa * C

@@ -210,24 +210,43 @@ def rn_study(seed: int, size: int):
     r_n | a* on all-'a' text: host construction time, where the D-SFA is
     placed (LDS image, global table with hot rows, or over the state cap and
     matched by the speculative kernel), GPU throughput, and the oracle's
-    sequential DFA on one core over the same bytes (also the parity check)."""
+    sequential DFA on one core over the same bytes (also the parity check).
+    Two tables over the default cap are also matched through an on-the-fly
+    D-SFA (the on-the-fly remark of Section 5.1) built from the first MiB of
+    their input: r500, and a 60-keyword dictionary on keyword text."""
     import numpy as np
     import torch
     import paper_1405_0562_amd as sfa
     import workloads as W
     big = 1_100_000   # state cap that admits the D-SFAs of r500 and r_a (about 10^6 states)
-    cases = [("r5", W.rn_regex(5), 5, None), ("r50", W.rn_regex(50), 50, None),
-             ("r500, default cap", W.rn_regex(500), 500, None), ("r500", W.rn_regex(500), 500, big),
-             ("r_a", W.ra_regex(500), None, big)]
+    kw60 = W.c3_keywords(seed, count=60)
+    # on-the-fly rows: (runs start every, run bytes) of the sample walk; r500's
+    # runs match the walk's pieces at this size (512 bytes), whose starts
+    # fall on 125 phases of the 1000-byte period
+    cases = [("r5", W.rn_regex(5), 5, None, None), ("r50", W.rn_regex(50), 50, None, None),
+             ("r500, default cap", W.rn_regex(500), 500, None, None),
+             ("r500, default cap, on the fly", W.rn_regex(500), 500, None, (512, 512)),
+             ("r500", W.rn_regex(500), 500, big, None),
+             ("r_a", W.ra_regex(500), None, big, None),
+             ("60 keywords, default cap", W.c3_regex(kw60), -1, None, None),
+             ("60 keywords, default cap, on the fly", W.c3_regex(kw60), -1, None, (256, 4096))]
     rows = []
     out = torch.empty(2, dtype=torch.int32, device="cuda")
-    for name, rx, n, cap in cases:
+    inputs = {}
+    for name, rx, n, cap, lazy in cases:
         print("[rn study] %s: building input and automata" % name, file=sys.stderr, flush=True)
-        data = W.rn_input(seed, n, size) if n else np.full(size, ord("a"), dtype=np.uint8)
+        if n not in inputs:
+            inputs.clear()
+            inputs[n] = (W.rn_input(seed, n, size) if n and n > 0 else
+                         W.c3_input(seed, size, kw60, rate=1e-6) if n == -1 else np.full(size, ord("a"), dtype=np.uint8))
+        data = inputs[n]
         t0 = time.perf_counter()
-        comp = sfa.compile(rx) if cap is None else sfa.compile(rx, sfa_cap=cap)
+        if lazy:
+            comp = sfa.compile(rx, sfa_cap=0).build_lazy(data[:1 << 20], start_every=lazy[0], walk_bytes=lazy[1])
+        else:
+            comp = sfa.compile(rx) if cap is None else sfa.compile(rx, sfa_cap=cap)
         compile_s = time.perf_counter() - t0
-        table = sfa.load(comp)
+        table = sfa.load(comp, profile_sample=data[:1 << 20] if lazy else None)
         x = torch.from_numpy(data).cuda()
         use_sfa = comp.info.n_sfa > 0
         fn = sfa.match if use_sfa else sfa.match_speculative
@@ -248,6 +267,8 @@ def rn_study(seed: int, size: int):
         info = table.info
         comp_info = (comp.info.n_dfa, comp.info.n_sfa)
         placement = ("speculative (D-SFA over the state cap)" if not use_sfa else
+                     "on the fly from the first MiB (runs of %d bytes every %d), global table, %d hot rows in LDS"
+                     % (lazy[1], lazy[0], info["hot_rows"]) if lazy else
                      "LDS image, strides %s" % [s for s, bit in ((1, 2), (2, 4), (4, 16)) if info["strides"] & bit]
                      if info["table_in_lds"] else "global table, %d hot rows in LDS" % info["hot_rows"])
         del table, comp

@@ -122,8 +122,9 @@ void       sfa_compiled_free(sfa_compiled *c);
  * transition a run takes for the first time is constructed then (state
  * f' = f followed by the DFA transition, looked up among the states built so
  * far), and at max_states states (identity included) construction stops
- * and a run that needs a new state ends there.  Transitions that no run took
- * stay unbuilt: SFA_UNBUILT in the descriptor's sfa_next.  The partial D-SFA
+ * and a run that needs a new state ends there.  Then every transition no run
+ * took is filled in when its target mapping is among the states built;
+ * the others stay unbuilt: SFA_UNBUILT in the descriptor's sfa_next.  The partial D-SFA
  * replaces the compilation's empty one (info.n_sfa = states built,
  * info.sfa_lazy = 1) and is loaded like a complete one (sfa_load_table).
  * The matchers walk it with the global-table walk: a piece that reaches an

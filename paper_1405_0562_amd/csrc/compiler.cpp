@@ -986,6 +986,19 @@ extern "C" sfa_status sfa_compiled_build_lazy(sfa_compiled *c, const uint8_t *sa
                 f = t;
             }
         }
+        // close the transitions among the states built: an edge no run took
+        // is filled in when its target mapping is one of them (no new
+        // state), so a walk leaves the built set only for a mapping no run
+        // reached
+        for (uint32_t f = 0; f < m; ++f)
+            for (uint32_t k = 0; k < C; ++k) {
+                if (snext[(size_t)f * C + k] != SFA_UNBUILT) continue;
+                const uint16_t *row = &rows[(size_t)f * n];
+                const uint16_t *col = cols[k].data();
+                for (uint32_t q = 0; q < n; ++q) tmp[q] = col[row[q]];
+                const uint32_t t = tab.find(tmp.data(), RowTable::hash(tmp.data(), n), slot);
+                if (t != UINT32_MAX) snext[(size_t)f * C + k] = t;
+            }
         c->n_sfa = m;
         c->lazy = 1;
         c->sfa_next.swap(snext);

@@ -110,10 +110,17 @@ struct MatchArgs {
 };
 
 // A parked piece: it reached an unbuilt D-SFA transition at byte pos, in
-// D-SFA state `state` (built); its bytes run to end.
+// D-SFA state `state` (built); its bytes run to end.  When the mapping of
+// `state` takes at most kParkVals distinct values, the piece's lane follows
+// each of them through the DFA over bytes [pos, end) once, after its walk:
+// vals[i] ends in res[i] (nvals of them; kParkMany: more values, every start
+// state is followed in the composition instead).
+constexpr uint32_t kParkVals = 4, kParkMany = 0xFFFFFFFFu;
 struct ParkRec {
     uint64_t pos, end;
-    uint32_t state, pad;
+    uint32_t state, nvals;
+    uint16_t vals[kParkVals], res[kParkVals];
+    uint32_t pad[2];
 };
 
 // piece id of a parked piece among the block's piece ids
@@ -129,11 +136,70 @@ __device__ __forceinline__ uint32_t parked_apply(const MatchArgs &a, MapAt map_a
     const uint64_t pos = __hip_atomic_load(&r->pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t end = __hip_atomic_load(&r->end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t st = __hip_atomic_load(&r->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t nv = __hip_atomic_load(&r->nvals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t y = map_at(st, x);
+    if (nv != kParkMany) {
+        // the piece's lane followed every value of the mapping: look y up
+        const uint32_t *w = (const uint32_t *)r->vals;   // vals, then res: four u32 words
+        uint32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = __hip_atomic_load(w + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t out = y;
+#pragma unroll
+        for (uint32_t i = 0; i < kParkVals; ++i) {
+            const uint32_t vi = (v[i / 2] >> (16 * (i & 1))) & 0xffffu;
+            const uint32_t ri = (v[2 + i / 2] >> (16 * (i & 1))) & 0xffffu;
+            out = (i < nv && vi == y) ? ri : out;
+        }
+        return out;
+    }
     const uint8_t *dn = (const uint8_t *)a.dnext;
     const uint32_t rb = 2 * a.n_classes;
     for (uint64_t i = pos; i < end; ++i) y = *(const uint16_t *)(dn + y * rb + a.cls[a.in[i]]);
     return y;
+}
+
+// The lane of a parked piece completes its record: the piece's end, and the
+// distinct values of its state's mapping (if at most kParkVals) each
+// followed through the DFA over the rest of the piece, all together.
+__device__ __forceinline__ void finish_parked(const MatchArgs &a, ParkRec *r, uint64_t end) {
+    r->end = end;
+    const uint64_t pos = r->pos;
+    const uint32_t st = r->state, n = a.n_dfa;
+    uint32_t v[kParkVals], nv = 0;
+    for (uint32_t q = 0; q < n && nv <= kParkVals; ++q) {
+        const uint32_t y = n <= 256 ? a.map[(size_t)st * n + q] : ((const uint16_t *)a.map)[(size_t)st * n + q];
+        bool seen = false;
+#pragma unroll
+        for (uint32_t i = 0; i < kParkVals; ++i) seen |= i < nv && v[i] == y;
+        if (!seen) {
+            if (nv < kParkVals) {
+#pragma unroll
+                for (uint32_t i = 0; i < kParkVals; ++i) v[i] = i == nv ? y : v[i];
+            }
+            ++nv;
+        }
+    }
+    if (nv > kParkVals) {
+        r->nvals = kParkMany;
+        return;
+    }
+    const uint8_t *dn = (const uint8_t *)a.dnext;
+    const uint32_t rb = 2 * a.n_classes;
+    uint32_t y[kParkVals];
+#pragma unroll
+    for (uint32_t i = 0; i < kParkVals; ++i) y[i] = i < nv ? v[i] : v[0];
+    for (uint64_t i = pos; i < end; ++i) {
+        const uint32_t c = a.cls[a.in[i]];
+#pragma unroll
+        for (uint32_t j = 0; j < kParkVals; ++j) y[j] = *(const uint16_t *)(dn + y[j] * rb + c);
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kParkVals; ++i) {
+        r->vals[i] = (uint16_t)(i < nv ? v[i] : 0);
+        r->res[i] = (uint16_t)(i < nv ? y[i] : 0);
+    }
+    r->nvals = nv;
 }
 
 // Phase 1 of a composition: the elements 0..E-1 (mappings, in text order) are
@@ -910,7 +976,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
         if constexpr (PARTIAL) {
             if (st[k] == parked) {
                 ids[k] = kParkedId;
-                a.park[((size_t)blockIdx.x * TB + threadIdx.x) * K + k].end = end[k];
+                finish_parked(a, a.park + ((size_t)blockIdx.x * TB + threadIdx.x) * K + k, end[k]);
             }
         }
     }

@@ -70,6 +70,20 @@ def test_example1_run_builds_the_visited_states():
     _check_consistent(a)
 
 
+def test_closure_fills_edges_between_built_states():
+    # "aab": f0 -a-> f1 -a-> f3 -b-> f3 (f3 = the constant mapping to the
+    # sink); the edge f3 -a-> f3 was not taken but its target is built
+    c, a = _lazy("(ab)*", b"aab", start_every=3, walk_bytes=3)
+    a_cls, b_cls = a["byte_class"][ord("a")], a["byte_class"][ord("b")]
+    assert c.info.n_sfa == 3
+    sink = int(a["dfa_next"][0, b_cls])
+    assert a["sfa_map"][2].tolist() == [sink] * 3
+    assert a["sfa_next"][2, a_cls] == 2 and a["sfa_next"][2, b_cls] == 2
+    # f1 -b-> f4 leads to a mapping no run reached: unbuilt
+    assert a["sfa_next"][1, b_cls] == UNBUILT
+    _check_consistent(a)
+
+
 @pytest.mark.parametrize("rx", [W.REGEX_C1, W.REGEX_C2, W.rn_regex(5), "(([02468][13579]){5})*",
                                 W.c3_regex(W.c3_keywords(0)[:4])])
 def test_lazy_states_are_states_of_the_complete_dsfa(rx):

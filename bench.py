@@ -280,6 +280,48 @@ def rn_study(seed: int, size: int):
     return {"rows": rows}
 
 
+def batch_study(seed: int, n_docs: int, piece: int, units: int, reps: int):
+    """The batch kernel alone on the batching workload with fixed options
+    (for profiler passes): plan, upload, ``reps`` launches, parity of the
+    last launch against the oracle on a sample of the documents."""
+    import numpy as np
+    import torch
+    import paper_1405_0562_amd as sfa
+    import workloads as W
+    from oracle.automata import compile_regex
+    from oracle import scan
+
+    regexes = W.c4_regexes(seed)
+    tables = [sfa.load(sfa.compile(rx)) for rx in regexes]
+    data, off = W.c4_docs(seed, n_docs)
+    x = torch.from_numpy(data).cuda()
+    nt = len(tables)
+    jobs = np.array([(d, t) for d in range(n_docs) for t in range(nt)], dtype=np.uint32)
+    b = sfa.Batch(tables, off, jobs, sfa.BatchOptions(piece, units))
+    b.run(x)
+    torch.cuda.synchronize()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(reps):
+        b.run(x)
+    e_ev.record()
+    torch.cuda.synchronize()
+    ms = s_ev.elapsed_time(e_ev) / reps
+    got = b.out.cpu().numpy()
+    dfas = [compile_regex(rx) for rx in regexes]
+    tabs = [scan.table_u32(d) for d in dfas]
+    ok = True
+    for d in range(0, n_docs, max(1, n_docs // 500)):
+        doc = data[off[d]:off[d + 1]]
+        for t in range(nt):
+            q = scan.scan(dfas[t], doc, table=tabs[t])
+            ok = ok and got[d * nt + t].tolist() == [q, int(dfas[t].accept[q])]
+    return {"workload": "%d docs x %d regexes, %d bytes" % (n_docs, nt, int(off[-1])),
+            "options": {"piece_bytes": piece, "units_per_lane": units, "tables_in_lds": b.info["tables_in_lds"]},
+            "n_units": b.info["n_units"], "launches": reps + 1, "batch_ms": ms,
+            "docs_per_s": n_docs / (ms * 1e-3), "parity_sampled": ok}
+
+
 def cpu_baseline_nfa_sets(rx, inputs):
     """The oracle's NFA run (position automaton, from I) over each input:
     (final state set as a bit mask, accept) -- the N-SFA result's definition."""
@@ -624,8 +666,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device-to-device copy of the workload size (counter calibration)")
-    ap.add_argument("--study", choices=["crossover", "rn", "nsfa"], default=None,
+    ap.add_argument("--study", choices=["crossover", "rn", "nsfa", "batch"], default=None,
                     help="run a study instead of the benchmark and print its JSON")
+    ap.add_argument("--batch-piece", type=int, default=2048, help="--study batch: piece bytes")
+    ap.add_argument("--batch-units", type=int, default=2, help="--study batch: pieces per lane")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -639,6 +683,10 @@ def main():
         return
     if args.study == "nsfa":
         print(json.dumps({"study": "D-SFA and N-SFA", **nsfa_study(args.seed, 1 << 28)}), flush=True)
+        return
+    if args.study == "batch":
+        print(json.dumps({"study": "batch kernel", **batch_study(args.seed, args.batch_docs, args.batch_piece,
+                                                                 args.batch_units, args.steps)}), flush=True)
         return
     if args.study == "rn":
         print(json.dumps({"study": "r_n scalability and placement", **rn_study(args.seed, 1 << 30)}), flush=True)

@@ -246,7 +246,8 @@ def rn_study(seed: int, size: int):
         else:
             comp = sfa.compile(rx) if cap is None else sfa.compile(rx, sfa_cap=cap)
         compile_s = time.perf_counter() - t0
-        table = sfa.load(comp, profile_sample=data[:1 << 20] if lazy else None)
+        # hot rows (global-table walk) ranked by a walk over the first MiB
+        table = sfa.load(comp, profile_sample=data[:1 << 20])
         x = torch.from_numpy(data).cuda()
         use_sfa = comp.info.n_sfa > 0
         fn = sfa.match if use_sfa else sfa.match_speculative
@@ -266,11 +267,12 @@ def rn_study(seed: int, size: int):
         (cpu_s, want), = cpu_baseline_sizes(rx, [data], budget_s=0.0)
         info = table.info
         comp_info = (comp.info.n_dfa, comp.info.n_sfa)
+        vec = ", vector re-walks of cold words" if info["vector_redo"] else ""
         placement = ("speculative (D-SFA over the state cap)" if not use_sfa else
-                     "on the fly from the first MiB (runs of %d bytes every %d), global table, %d hot rows in LDS"
-                     % (lazy[1], lazy[0], info["hot_rows"]) if lazy else
+                     "on the fly from the first MiB (runs of %d bytes every %d), global table, %d hot rows in LDS%s"
+                     % (lazy[1], lazy[0], info["hot_rows"], vec) if lazy else
                      "LDS image, strides %s" % [s for s, bit in ((1, 2), (2, 4), (4, 16)) if info["strides"] & bit]
-                     if info["table_in_lds"] else "global table, %d hot rows in LDS" % info["hot_rows"])
+                     if info["table_in_lds"] else "global table, %d hot rows in LDS%s" % (info["hot_rows"], vec))
         del table, comp
         rows.append({"regex": name, "n_dfa": comp_info[0], "n_sfa": comp_info[1],
                      "compile_s": compile_s, "placement": placement, "product_table": info["product_table"],

@@ -254,7 +254,9 @@ typedef struct sfa_table_info {
     uint32_t product_table;  /* 1: compositions reduce D-SFA ids through the product table */
     uint64_t device_bytes;   /* bytes used in d_buf */
     uint32_t partial;        /* 1: some D-SFA transitions are unbuilt (on-the-fly D-SFA) */
-    uint32_t reserved;
+    uint32_t vector_redo;    /* 1: the profiling walk spent more than 0.2 % of its visits beyond the
+                                hot rows, so the global-table walk re-walks the words of many cold
+                                pieces of a wave at once with vector loads */
 } sfa_table_info;
 
 sfa_status sfa_table_device_bytes(const sfa_table_desc *desc, const sfa_load_options *opts,

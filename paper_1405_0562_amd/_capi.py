@@ -63,7 +63,7 @@ class TableInfo(ctypes.Structure):
                 ("q0", ctypes.c_uint32), ("next_bytes", ctypes.c_uint32), ("map_bytes", ctypes.c_uint32),
                 ("table_in_lds", ctypes.c_uint32), ("hot_rows", ctypes.c_uint32),
                 ("strides", ctypes.c_uint32), ("product_table", ctypes.c_uint32),
-                ("device_bytes", ctypes.c_uint64), ("partial", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("device_bytes", ctypes.c_uint64), ("partial", ctypes.c_uint32), ("vector_redo", ctypes.c_uint32)]
 
 
 class Plan(ctypes.Structure):

@@ -21,6 +21,7 @@ HIP_SOURCES = [
     "runtime.hip", "batch.hip", "stream.hip",
     "walk_lds_s1.hip", "walk_lds_s2.hip", "walk_lds_s4.hip",
     "walk_global_u8.hip", "walk_global_u16.hip", "walk_global_u32.hip", "walk_partial.hip",
+    "walk_partial_vector.hip", "walk_vector.hip",
 ]
 BUILD_DIR = os.path.join(HERE, "_build")
 HIP_FLAGS = [

@@ -65,6 +65,7 @@ struct Layout {
     uint32_t himg_bytes = 0;
     uint32_t renumbered = 0; // 1: D-SFA ids were renumbered by visit count
     uint32_t partial = 0;    // 1: on-the-fly D-SFA with unbuilt transitions (largest id of next_w)
+    uint32_t vector_redo = 0; // 1: global walk re-walks cold words with vector loads (set by pack)
 };
 
 inline int stride_index(uint32_t S) { return S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : -1; }

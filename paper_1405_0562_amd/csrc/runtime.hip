@@ -170,6 +170,10 @@ bool product_defined(const sfa_table_desc *d) {
     return true;
 }
 
+// Share of the profiling walk's visits beyond the hot rows above which the
+// global walk uses vector re-walks (C3's keyword D-SFA: 3e-5; r500: most).
+constexpr double kVectorShare = 0.002;
+
 // LDS bytes the walk kernel needs besides the image: piece states + scratch.
 constexpr uint32_t kWalkExtraLds = kMaxIds * 4 + 16 + kScratchLds;
 
@@ -317,7 +321,8 @@ std::vector<uint32_t> trap_states(const sfa_table_desc *d) {
 // profiling walk (descending, ties by id).  The walk follows the sample bytes
 // (256 walkers over consecutive parts) or, without a sample, classes drawn
 // uniformly (256 walkers x 2048 steps, xorshift generator).
-std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_options *o) {
+std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_options *o, uint32_t H,
+                                  double *cold_share) {
     const uint32_t m = d->n_sfa, C = d->n_classes;
     std::vector<uint64_t> count(m, 0);
     const uint32_t W = 256;
@@ -349,12 +354,24 @@ std::vector<uint32_t> visit_order(const sfa_table_desc *d, const sfa_load_option
     // closed sets rank above every visited state (a count no walk reaches)
     const uint64_t top = ~0ull;
     const std::vector<uint32_t> traps = trap_states(d);
-    for (size_t i = 0; i < traps.size(); ++i) count[traps[i]] = top - i;
+    std::vector<uint8_t> is_trap(m, 0);
+    for (size_t i = 0; i < traps.size(); ++i) {
+        count[traps[i]] = top - i;
+        is_trap[traps[i]] = 1;
+    }
     std::vector<uint32_t> ids(m);
     for (uint32_t i = 0; i < m; ++i) ids[i] = i;
     std::stable_sort(ids.begin() + 1, ids.end(), [&](uint32_t a, uint32_t b) { return count[a] > count[b]; });
     std::vector<uint32_t> perm(m);   // old id -> new id
     for (uint32_t i = 0; i < m; ++i) perm[ids[i]] = i;
+    // share of the profiling walk's visits that land beyond the first H rows
+    double all = 0, cold = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (is_trap[i]) continue;
+        all += (double)count[i];
+        if (perm[i] >= H) cold += (double)count[i];
+    }
+    if (cold_share) *cold_share = all > 0 ? cold / all : 0.0;
     return perm;
 }
 
@@ -363,14 +380,19 @@ void put(std::vector<uint8_t> &img, uint64_t off, uint64_t i, T v) {
     std::memcpy(&img[off + i * sizeof(T)], &v, sizeof(T));
 }
 
-void pack(const sfa_table_desc *d0, const sfa_load_options *o, const Layout &L, std::vector<uint8_t> &img) {
+void pack(const sfa_table_desc *d0, const sfa_load_options *o, Layout &L, std::vector<uint8_t> &img) {
     img.assign(L.total, 0);
     const uint32_t C = L.C;
     // renumbered copies of the D-SFA arrays (new id = perm[old id])
     sfa_table_desc dd = *d0;
     std::vector<uint32_t> rnext, rmap;
     if (L.renumbered) {
-        const std::vector<uint32_t> perm = visit_order(d0, o);
+        double cold_share = 0;
+        const std::vector<uint32_t> perm = visit_order(d0, o, L.hot_rows, &cold_share);
+        // a walk that often leaves the hot rows re-walks its cold words with
+        // vector loads (many pieces of a wave at once) rather than one lane
+        // at a time
+        L.vector_redo = L.himg_bytes && L.hot_rows < d0->n_sfa && cold_share > kVectorShare ? 1 : 0;
         const uint32_t m = d0->n_sfa, n = d0->n_dfa;
         rnext.resize((uint64_t)m * C);
         rmap.resize((uint64_t)m * n);
@@ -540,6 +562,7 @@ extern "C" sfa_status sfa_table_get_info(const sfa_table *t, sfa_table_info *out
     out->product_table = t->L.mul_bytes ? 1u : 0u;
     out->device_bytes = t->L.total;
     out->partial = t->L.partial;
+    out->vector_redo = t->L.vector_redo;
     return SFA_OK;
 }
 
@@ -613,12 +636,18 @@ __global__ __launch_bounds__(kSpecWaves * 64) void k_spec_walk(MatchArgs a) {
 }
 
 
-bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, bool partial) {
+bool special_shape(uint32_t K, uint32_t G, uint32_t D, uint32_t TB) {
 #define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
-    if (partial) {
-        SFA_PARTIAL_SHAPES(SFA_SHAPE_OK)
-        return false;
-    }
+    SFA_SPECIAL_SHAPES(SFA_SHAPE_OK)
+#undef SFA_SHAPE_OK
+    return false;
+}
+
+// A partial D-SFA has kernels for the special shapes only; a table with
+// vector re-walks uses them for those shapes and the plain kernel otherwise.
+bool global_shape_ok(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, bool partial) {
+    if (partial) return special_shape(K, G, D, TB);
+#define SFA_SHAPE_OK(k, g, d, tb) if (K == k && G == g && D == d && TB == tb) return true;
     SFA_GLOBAL_SHAPES(SFA_SHAPE_OK)
 #undef SFA_SHAPE_OK
     return false;
@@ -960,10 +989,21 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         a.map_lds = a.map_bytes <= a.region_bytes;
         const size_t lds = (size_t)g.region + a.mul_lds + 16;
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");
+        const bool vec = t->L.vector_redo && special_shape(P.K, P.G, P.D, P.TB);
         if (t->L.partial) {
-            if (t->L.next_w == 1) e = dispatch_partial<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
-            else if (t->L.next_w == 2) e = dispatch_partial<uint16_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
-            else e = dispatch_partial<uint32_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            if (t->L.next_w == 1)
+                e = vec ? dispatch_special<uint8_t, true, true>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a)
+                        : dispatch_special<uint8_t, true, false>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            else if (t->L.next_w == 2)
+                e = vec ? dispatch_special<uint16_t, true, true>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a)
+                        : dispatch_special<uint16_t, true, false>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            else
+                e = vec ? dispatch_special<uint32_t, true, true>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a)
+                        : dispatch_special<uint32_t, true, false>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+        } else if (vec) {
+            if (t->L.next_w == 1) e = dispatch_special<uint8_t, false, true>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            else if (t->L.next_w == 2) e = dispatch_special<uint16_t, false, true>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
+            else e = dispatch_special<uint32_t, false, true>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
         } else if (t->L.next_w == 1) {
             e = dispatch_global<uint8_t>(P.K, P.G, P.D, P.TB, P.blocks, lds, s, a);
         } else if (t->L.next_w == 2) {

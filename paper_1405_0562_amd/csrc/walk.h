@@ -31,6 +31,7 @@ constexpr uint32_t kMulMax = 16 * 1024;      // product table bytes at most (u8 
 constexpr uint32_t kIdRun = 4096;            // product mode: blocks per level-1 run
 constexpr uint64_t kWsHeader = 4096;         // workspace control words: [0] top level, [1 + r] level-1 run r
 constexpr uint32_t kMaxRuns = kWsHeader / 4 - 1;
+constexpr uint32_t kVectorRedo = 8;          // global walk: cold pieces of a wave above which the word is re-walked with vector loads
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
@@ -692,7 +693,7 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 // its walk, the piece ids and the composition scratch take the end of that
 // region ([region_bytes, R)) and [0, region_bytes) is free for staging;
 // [R, R + mul_lds) the product table (product mode); then the flag word.
-template <int K, int G, int D, typename NT, int TB, bool PARTIAL>
+template <int K, int G, int D, typename NT, int TB, bool PARTIAL, bool VEC>
 __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     constexpr uint32_t ROWS = 256;                          // rows follow the class table
@@ -820,7 +821,37 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
         if (any) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                for (uint64_t m = __ballot(t[k] == cold); m; m &= m - 1) {
+                uint64_t m = __ballot(t[k] == cold);
+                if (VEC && __builtin_popcountll(m) > kVectorRedo) {
+                    // many pieces left the hot rows (a table whose visited
+                    // states do not fit LDS): each walks its word again with
+                    // vector loads, all at once; the wait for them also waits
+                    // for the input loads in flight, which costs less than
+                    // that many scalar chains one after another
+                    if (t[k] == cold) {
+                        uint64_t s = t0[k] == cold ? cid[k] : t0[k];
+                        int at = -1;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (at < 0) {
+                                const uint32_t u = *(const NT *)(tab + (s * C + (c[i][k] >> 1)) * sizeof(NT));
+                                if (PARTIAL && u == kUnbuilt)
+                                    at = i;
+                                else
+                                    s = u;
+                            }
+                        }
+                        if (PARTIAL && at >= 0) {
+                            park_at(k, (uint64_t)(cin - a.in) + body[k] + boff + (uint32_t)at, (uint32_t)s);
+                            t[k] = parked;
+                        } else {
+                            t[k] = s < H ? (uint32_t)s : cold;
+                        }
+                        cid[k] = (uint32_t)s;
+                    }
+                    m = 0;
+                }
+                for (; m; m &= m - 1) {
                     const uint32_t l = (uint32_t)__builtin_ctzll(m);
                     uint32_t cl[4];
 #pragma unroll
@@ -1024,9 +1055,10 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     X(2, 128, 1, 512) X(3, 128, 1, 512) X(4, 128, 1, 512) \
     X(1, 64, 2, 1024) X(2, 64, 2, 1024) X(1, 128, 2, 1024)
 
-// Shapes of the global-table walk for a partial (on-the-fly) D-SFA: the
-// default plan and the shapes it falls back to for short chunks.
-#define SFA_PARTIAL_SHAPES(X) X(4, 128, 1, 512) X(2, 128, 1, 512) X(1, 64, 2, 512)
+// Shapes of the global-table walk for a partial (on-the-fly) D-SFA or a
+// table whose walk often leaves the hot rows (vector re-walks): the default
+// plan and the shapes it falls back to for short chunks.
+#define SFA_SPECIAL_SHAPES(X) X(4, 128, 1, 512) X(2, 128, 1, 512) X(1, 64, 2, 512)
 
 // Once per kernel and device (runtime.hip): checks that the kernel has no
 // static LDS (its dynamic LDS starts at address 0, which lds_u8/lds_u16
@@ -1061,20 +1093,22 @@ template <typename NT>
 hipError_t dispatch_global(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
                            hipStream_t s, const MatchArgs &a) {
 #define SFA_SHAPE_LAUNCH(k, g, d, tb) \
-    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb, false>, blocks, tb, lds, s, a);
+    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb, false, false>, blocks, tb, lds, s, a);
     SFA_GLOBAL_SHAPES(SFA_SHAPE_LAUNCH)
 #undef SFA_SHAPE_LAUNCH
     return hipErrorInvalidValue;
 }
 
-// The same for a partial D-SFA (SFA_PARTIAL_SHAPES), instantiated for the
-// three id widths in walk_partial.hip.
-template <typename NT>
-hipError_t dispatch_partial(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
+// The same for a partial D-SFA and/or vector re-walks (SFA_SPECIAL_SHAPES),
+// instantiated for the three id widths in walk_partial.hip (partial) and
+// walk_vector.hip (complete tables with vector re-walks).
+template <typename NT, bool PARTIAL, bool VEC>
+hipError_t dispatch_special(uint32_t K, uint32_t G, uint32_t D, uint32_t TB, uint32_t blocks, size_t lds,
                             hipStream_t s, const MatchArgs &a) {
 #define SFA_SHAPE_LAUNCH(k, g, d, tb) \
-    if (K == k && G == g && D == d && TB == tb) return launch(k_sfa_global<k, g, d, NT, tb, true>, blocks, tb, lds, s, a);
-    SFA_PARTIAL_SHAPES(SFA_SHAPE_LAUNCH)
+    if (K == k && G == g && D == d && TB == tb) \
+        return launch(k_sfa_global<k, g, d, NT, tb, PARTIAL, VEC>, blocks, tb, lds, s, a);
+    SFA_SPECIAL_SHAPES(SFA_SHAPE_LAUNCH)
 #undef SFA_SHAPE_LAUNCH
     return hipErrorInvalidValue;
 }
@@ -1091,11 +1125,17 @@ extern SFA_DISPATCH_SHAPE(4);
 extern SFA_DISPATCH_GLOBAL(uint8_t);
 extern SFA_DISPATCH_GLOBAL(uint16_t);
 extern SFA_DISPATCH_GLOBAL(uint32_t);
-#define SFA_DISPATCH_PARTIAL(NT) \
-    template hipError_t dispatch_partial<NT>(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, size_t, hipStream_t, \
-                                             const MatchArgs &)
-extern SFA_DISPATCH_PARTIAL(uint8_t);
-extern SFA_DISPATCH_PARTIAL(uint16_t);
-extern SFA_DISPATCH_PARTIAL(uint32_t);
+#define SFA_DISPATCH_SPECIAL(NT, P, V) \
+    template hipError_t dispatch_special<NT, P, V>(uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, size_t, \
+                                                   hipStream_t, const MatchArgs &)
+extern SFA_DISPATCH_SPECIAL(uint8_t, true, false);
+extern SFA_DISPATCH_SPECIAL(uint16_t, true, false);
+extern SFA_DISPATCH_SPECIAL(uint32_t, true, false);
+extern SFA_DISPATCH_SPECIAL(uint8_t, true, true);
+extern SFA_DISPATCH_SPECIAL(uint16_t, true, true);
+extern SFA_DISPATCH_SPECIAL(uint32_t, true, true);
+extern SFA_DISPATCH_SPECIAL(uint8_t, false, true);
+extern SFA_DISPATCH_SPECIAL(uint16_t, false, true);
+extern SFA_DISPATCH_SPECIAL(uint32_t, false, true);
 
 }  // namespace sfa_rt

@@ -3,7 +3,7 @@
 #include "walk.h"
 
 namespace sfa_rt {
-SFA_DISPATCH_PARTIAL(uint8_t);
-SFA_DISPATCH_PARTIAL(uint16_t);
-SFA_DISPATCH_PARTIAL(uint32_t);
+SFA_DISPATCH_SPECIAL(uint8_t, true, false);
+SFA_DISPATCH_SPECIAL(uint16_t, true, false);
+SFA_DISPATCH_SPECIAL(uint32_t, true, false);
 }  // namespace sfa_rt

@@ -10,7 +10,9 @@ scheduler loop body:
    (memory-admitted continuous batching: requests that arrive while earlier
    batches run join the next batch, which overlaps with them on the device);
 3. launch: admitted requests form one batch (one job per request) launched on
-   the next stream; requests of at least ``big_bytes`` go alone through the
+   the next stream; requests of at least ``big_bytes``, and requests for a
+   table the batch kernel does not take (``backend.batchable``: no stride-1
+   walk image, e.g. a large or on-the-fly D-SFA), go alone through the
    single-stream matcher instead, which splits them over the whole GPU.
 
 The backend owns device work; ``GpuBackend`` drives libsfa.so, the CPU
@@ -145,7 +147,7 @@ class Server:
         launched = 0
         while self.waiting and len(self.inflight) < self.max_inflight:
             head = self.waiting[0]
-            if head.nbytes >= self.big_bytes:
+            if head.nbytes >= self.big_bytes or not self._batchable(head):
                 off = self.pool.alloc(head.nbytes)
                 if off is None:
                     break
@@ -156,7 +158,7 @@ class Server:
             else:
                 batch, total = [], 0
                 for r in self.waiting:
-                    if r.nbytes >= self.big_bytes or len(batch) >= self.max_batch:
+                    if r.nbytes >= self.big_bytes or len(batch) >= self.max_batch or not self._batchable(r):
                         break
                     batch.append(r)
                     total += r.nbytes
@@ -177,6 +179,10 @@ class Server:
             self.n_launches += 1
             launched += 1
         return launched
+
+    def _batchable(self, r: Request) -> bool:
+        fn = getattr(self.backend, "batchable", None)
+        return True if fn is None else bool(fn(r.table))
 
     def step(self) -> tuple[int, int]:
         """One scheduler pass: (batches completed, batches launched)."""
@@ -217,6 +223,13 @@ class GpuBackend:
         self.Batch, self.BatchOptions = Batch, BatchOptions
         self.tables = list(tables)
         self.device = self.tables[0].device if device is None else device
+        # the batch plan takes the tables with a stride-1 walk image; requests
+        # for the others are matched alone
+        self._batch_ids = {}
+        for i, t in enumerate(self.tables):
+            if t.info["strides"] & 2 and not t.info["partial"]:
+                self._batch_ids[i] = len(self._batch_ids)
+        self.batch_tables = [t for i, t in enumerate(self.tables) if i in self._batch_ids]
         self.dev_pool = torch.empty(pool_bytes, dtype=torch.uint8, device=self.device)
         self.host_pool = torch.empty(pool_bytes, dtype=torch.uint8, pin_memory=True)
         self.host_np = self.host_pool.numpy()
@@ -254,9 +267,9 @@ class GpuBackend:
                 self.launch_single(Request(-1, t, x, 0.0), 0)[0].synchronize()
         small = np.zeros(4096, dtype=np.uint8)
         for _ in self.streams:
-            reqs = [Request(-1, t, small, 0.0) for t in range(len(self.tables))]
-            h = self.launch_batch(reqs, 0)
-            h[0].synchronize()
+            reqs = [Request(-1, t, small, 0.0) for t in self._batch_ids]
+            if len(reqs) >= 2:
+                self.launch_batch(reqs, 0)[0].synchronize()
         self.torch.cuda.synchronize(self.device)
 
     def _stream(self):
@@ -280,6 +293,9 @@ class GpuBackend:
         self.next_slot += 1
         return buf[:n]
 
+    def batchable(self, table: int) -> bool:
+        return table in self._batch_ids
+
     def launch_batch(self, requests, off):
         torch = self.torch
         if len(requests) == 1:
@@ -289,9 +305,10 @@ class GpuBackend:
         lens = np.array([r.nbytes for r in requests], dtype=np.int64)
         doc_off = np.zeros(len(requests) + 1, dtype=np.int64)
         np.cumsum(lens, out=doc_off[1:])
-        jobs = np.stack([np.arange(len(requests)), [r.table for r in requests]], axis=1).astype(np.uint32)
+        jobs = np.stack([np.arange(len(requests)), [self._batch_ids[r.table] for r in requests]],
+                        axis=1).astype(np.uint32)
         with torch.cuda.stream(s):
-            b = self.Batch(self.tables, doc_off, jobs, self.options, stream=s, ws=self.stream_ws[i],
+            b = self.Batch(self.batch_tables, doc_off, jobs, self.options, stream=s, ws=self.stream_ws[i],
                            out=self.stream_out[i])
             if b.ws is not self.stream_ws[i]:
                 self.stream_ws[i] = b.ws   # grown once for a larger plan, kept for the next ones
@@ -347,11 +364,15 @@ class FakeBackend:
     """CPU stand-in for tests: results from a callable, completion after a
     simulated service time measured on the caller's clock."""
 
-    def __init__(self, clock, result_fn, service_time=lambda nbytes: 1e-3 + nbytes / 1e9):
+    def __init__(self, clock, result_fn, service_time=lambda nbytes: 1e-3 + nbytes / 1e9, unbatchable=()):
         self.clock = clock
         self.result_fn = result_fn
         self.service_time = service_time
         self.launches = []
+        self.unbatchable = set(unbatchable)
+
+    def batchable(self, table: int) -> bool:
+        return table not in self.unbatchable
 
     def _launch(self, requests, big):
         t_done = self.clock() + self.service_time(sum(r.nbytes for r in requests))

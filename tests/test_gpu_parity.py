@@ -382,6 +382,24 @@ def test_every_global_launch_plan(product):
                 assert sfa.match(t, x, n_chunks=n_chunks, plan=plan).tolist() == want, (plan, n_chunks, t.info)
 
 
+def test_vector_rewalks_of_cold_words():
+    # a profile whose visits mostly miss the few staged rows switches the
+    # global walk to vector re-walks of cold words (complete and partial
+    # D-SFAs); both must still equal the oracle
+    rx = W.rn_regex(40)
+    sample = W.rn_input(9, 40, 1 << 20)
+    words = W.rn_input(10, 40, (4 << 20) + 80 * 3)
+    full = sfa.load(sfa.compile(rx, sfa_cap=100_000), profile_sample=sample, lds_budget=2048)
+    lazy = sfa.load(sfa.compile(rx, sfa_cap=0).build_lazy(sample, start_every=64, walk_bytes=512, max_states=2000),
+                    profile_sample=sample, lds_budget=256)
+    for t in (full, lazy):
+        assert t.info["vector_redo"] == 1 and t.info["table_in_lds"] == 0
+        for data in (words, words[: (1 << 20) + 77]):
+            want = oracle_result(rx, data)
+            for n_chunks in (0, 1000, 65536):
+                assert run_table(t, rx, data, n_chunks) == want, (t.info["partial"], n_chunks)
+
+
 def test_dsfa_over_65536_states_uses_32_bit_ids():
     # r_128 has 4*128^2 + 2*128 = 65,792 D-SFA states: 32-bit walk-table
     # entries, read by the global-table walk with hot rows in LDS

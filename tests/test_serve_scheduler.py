@@ -89,6 +89,23 @@ def test_big_requests_go_alone_and_small_ones_batch():
     assert all(r.result == oracle_result(r) for r in srv.finished)
 
 
+def test_unbatchable_tables_go_alone():
+    # a table the batch kernel does not take (no stride-1 image, or an
+    # on-the-fly D-SFA) is matched alone, in arrival order with the rest
+    clock = Clock()
+    backend = FakeBackend(clock, oracle_result, service_time=lambda nb: 0.010 + nb / 1e8, unbatchable={1})
+    srv = Server(backend, pool_bytes=1 << 22, max_inflight=8, clock=clock)
+    for t in (0, 2, 1, 0, 2):
+        srv.submit(t, np.zeros(16, np.uint8))
+    srv.step()
+    kinds = [(h["big"], [r.table for r in h["req"]]) for h in backend.launches]
+    assert kinds == [(False, [0, 2]), (True, [1]), (False, [0, 2])]
+    while not srv.idle:
+        clock.t += 0.01
+        srv.step()
+    assert all(r.result == oracle_result(r) for r in srv.finished)
+
+
 def test_continuous_batching_overlaps_arrivals():
     clock = Clock()
     srv, be = make_server(clock, pool=1 << 22, max_inflight=4)

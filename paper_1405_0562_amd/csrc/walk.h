@@ -687,7 +687,15 @@ __global__ __launch_bounds__(TB) void k_sfa_lds(MatchArgs a) {
 // in order, so a vector load would also wait for the input in flight.  While
 // its state is cold, a piece keeps t = H and the state's id in cid.  The
 // input is loaded as in the LDS walk: G bytes of each piece per step, loads
-// issued D - 1 steps ahead.
+// issued D - 1 steps ahead (D = 1: the rolling ring described below).
+//
+// VEC: when more than kVectorRedo pieces of a wave end a word cold (tables
+// whose visited states do not fit LDS), they re-walk it all at once with
+// vector loads instead.  PARTIAL (on-the-fly D-SFA, the on-the-fly remark of
+// Section 5.1): an unbuilt transition reads as the largest id of NT; the
+// piece records where it stopped (ParkRec), moves to the parking row H + 1,
+// and its mapping is completed after the walk (finish_parked) and in the
+// block composition (parked_apply).
 //
 // LDS: [0, R) the hot image during the walk; once every wave has finished
 // its walk, the piece ids and the composition scratch take the end of that

@@ -216,7 +216,8 @@ class GpuBackend:
 
     def __init__(self, tables, pool_bytes: int = 1 << 30, n_streams: int = 3, piece_bytes: int = 4096,
                  units_per_lane: int = 2, device=None, max_batch_requests: int = 4096, result_slots: int = 64,
-                 ws_bytes: int = 32 << 20, warmup: bool = True, warmup_max_bytes: int = 64 << 20):
+                 ws_bytes: int = 32 << 20, warmup: bool = True, warmup_max_bytes: int = 64 << 20,
+                 direct_bytes: int = 1 << 20):
         import torch
         from .batch import Batch, BatchOptions
         self.torch = torch
@@ -244,6 +245,7 @@ class GpuBackend:
         # in order, so they share them, and serving allocates nothing
         self.max_batch_requests = max_batch_requests
         self.warmup_max_bytes = warmup_max_bytes
+        self.direct_bytes = direct_bytes
         self.stream_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=self.device) for _ in self.streams]
         self.stream_out = [torch.empty((max_batch_requests, 2), dtype=torch.int32, device=self.device)
                            for _ in self.streams]
@@ -278,15 +280,26 @@ class GpuBackend:
         return i, self.streams[i]
 
     def _stage(self, requests, off, stream):
+        """Copies the requests' bytes to dev_pool[off:] on `stream`: small
+        ones through the pinned pool (one host copy, then one asynchronous
+        transfer for all of them), requests of at least ``direct_bytes``
+        straight from their own memory (one transfer, no host copy)."""
         cur = off
-        for r in requests:
-            self.host_np[cur:cur + r.nbytes] = r.data
-            cur += r.nbytes
-        total = cur - off
+        run = off   # start of the pending run of small requests in the pinned pool
         with self.torch.cuda.stream(stream):
-            if total:
-                self.dev_pool[off:off + total].copy_(self.host_pool[off:off + total], non_blocking=True)
-        return total
+            for r in requests:
+                if r.nbytes >= self.direct_bytes:
+                    if cur > run:
+                        self.dev_pool[run:cur].copy_(self.host_pool[run:cur], non_blocking=True)
+                    self.dev_pool[cur:cur + r.nbytes].copy_(self.torch.from_numpy(r.data), non_blocking=True)
+                    cur += r.nbytes
+                    run = cur
+                else:
+                    self.host_np[cur:cur + r.nbytes] = r.data
+                    cur += r.nbytes
+            if cur > run:
+                self.dev_pool[run:cur].copy_(self.host_pool[run:cur], non_blocking=True)
+        return cur - off
 
     def _slot(self, n):
         buf = self.result_slots[self.next_slot % len(self.result_slots)]

@@ -668,15 +668,16 @@ struct Plan {
     uint32_t map_stride = 0, super_blocks = 0, n_super = 1, groups1 = 1, final_groups = 1, stage1 = 0, stage2 = 0;
     size_t ws_maps = 0, ws_groups = 0, ws_bytes = 0;   // workspace offsets and size
     size_t ws_park = 0;         // partial D-SFA: park records (one per piece), after the rest
+    uint32_t group_lds = 0;     // global walk: block-composition groups in the free LDS region
 };
 
 // Groups for a composition of E elements: about sqrt(E) groups, so that the
 // parallel phase (chains of E/G) and the serial phase (chains of G) balance,
-// within the LDS scratch and at most 4096 (group, state) pairs.
-uint32_t pick_groups(uint32_t E, uint32_t n_dfa) {
+// within `scratch` bytes of LDS and at most `max_pairs` (group, state) pairs.
+uint32_t pick_groups(uint32_t E, uint32_t n_dfa, uint64_t scratch = kScratchLds, uint64_t max_pairs = 4096) {
     uint32_t G = 1;
-    while ((uint64_t)(G * 2) * (G * 2) <= E && (uint64_t)G * 2 * n_dfa * 4 <= kScratchLds &&
-           (uint64_t)G * 2 * n_dfa <= 4096)
+    while ((uint64_t)(G * 2) * (G * 2) <= E && (uint64_t)G * 2 * n_dfa * 4 <= scratch &&
+           (uint64_t)G * 2 * n_dfa <= max_pairs)
         G *= 2;
     return G;
 }
@@ -850,6 +851,18 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         P.LPC = LPC;
         P.blocks = (uint32_t)(((uint64_t)P.n_chunks * LPC + TB - 1) / TB);
         P.groups = pick_groups(P.K * TB, t->L.n_dfa);
+        if (S == 0 && !t->L.mul_bytes) {
+            // global walk whose mapping rows stay in global memory: the
+            // block composition's groups go to the LDS the hot image frees,
+            // so there can be more of them, with shorter chains of global
+            // reads (C3: 16 groups of 128 pieces -> 32 of 64; measured 1.86 ->
+            // 1.78 ms; 64 groups of 32, 24 chains per thread: no faster)
+            const GlobalLds g = global_lds(t, P);
+            if ((uint64_t)t->L.map_w * t->L.n_sfa * t->L.n_dfa > g.free) {
+                P.group_lds = 1;
+                P.groups = pick_groups(P.K * TB, t->L.n_dfa, g.free, (uint64_t)TB * kGroupPairsPerThread);
+            }
+        }
     }
     P.stage_bytes = stage_bytes(t, P, speculative);
     plan_grid(P, t->L.n_dfa, !speculative && t->L.mul_bytes);
@@ -986,6 +999,7 @@ extern "C" sfa_status sfa_match_ex(const sfa_table *t, const uint8_t *d_in, uint
         const GlobalLds g = global_lds(t, P);
         a.region_bytes = g.free;
         a.mul_off = g.region;
+        a.group_lds = P.group_lds;
         a.map_lds = a.map_bytes <= a.region_bytes;
         const size_t lds = (size_t)g.region + a.mul_lds + 16;
         if (lds > t->lds_per_block) return sfa_fail(SFA_ERR_INVALID_ARG, "LDS plan exceeds the device limit");

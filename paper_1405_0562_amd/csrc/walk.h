@@ -32,6 +32,7 @@ constexpr uint32_t kIdRun = 4096;            // product mode: blocks per level-1
 constexpr uint64_t kWsHeader = 4096;         // workspace control words: [0] top level, [1 + r] level-1 run r
 constexpr uint32_t kMaxRuns = kWsHeader / 4 - 1;
 constexpr uint32_t kVectorRedo = 8;          // global walk: cold pieces of a wave above which the word is re-walked with vector loads
+constexpr uint32_t kGroupPairsPerThread = 12; // (group, state) chains a thread follows together from global rows
 
 inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
@@ -108,6 +109,7 @@ struct MatchArgs {
     uint32_t partial;
     struct ParkRec *park;    // [gridDim.x * K * TB], piece e of block b at b * K * TB + e
     const uint16_t *dnext;   // DFA transitions u16 [n_dfa * C] (class offsets in cls)
+    uint32_t group_lds;      // global walk: the block composition's groups at LDS offset 0 (the freed region)
 };
 
 // A parked piece: it reached an unbuilt D-SFA transition at byte pos, in
@@ -207,16 +209,16 @@ __device__ __forceinline__ void finish_parked(const MatchArgs &a, ParkRec *r, ui
 // cut into G groups of R consecutive elements; for every (group g, start
 // state q) pair, q is followed through the group's mappings, the earlier
 // mapping first (reverse composition, f . g = g o f), and the end state is
-// stored at out[g * n + q].  `get(e, x)` is mapping e applied to x.  Four
+// stored at out[g * n + q].  `get(e, x)` is mapping e applied to x.  P
 // pairs per thread are followed together to hide load latency.
-template <typename Get, typename Out>
+template <int P = 4, typename Get, typename Out>
 __device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, uint32_t G, uint32_t n,
                                               Out *out) {
     const uint32_t items = G * n;
-    for (uint32_t base = threadIdx.x; base < items; base += 4 * blockDim.x) {
-        uint32_t it[4], x[4], e0[4], e1[4];
+    for (uint32_t base = threadIdx.x; base < items; base += P * blockDim.x) {
+        uint32_t it[P], x[P], e0[P], e1[P];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < P; ++i) {
             it[i] = min(base + (uint32_t)i * blockDim.x, items - 1);
             const uint32_t g = it[i] / n;
             x[i] = it[i] - g * n;
@@ -225,14 +227,14 @@ __device__ __forceinline__ void follow_groups(Get get, uint32_t E, uint32_t R, u
         }
         for (uint32_t r = 0; r < R; ++r) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < P; ++i) {
                 const uint32_t e = e0[i] + r;
                 const uint32_t y = get(min(e, E - 1), x[i]);
                 x[i] = e < e1[i] ? y : x[i];
             }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < P; ++i)
             if (base + (uint32_t)i * blockDim.x < items) out[it[i]] = x[i];
     }
 }
@@ -275,7 +277,11 @@ __device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem,
             follow_groups(get, E, R, 1, n, out_map);
             return;
         }
-        follow_groups(get, E, R, G, n, target);
+        // rows from global memory: more chains at once to cover the latency
+        if (a.group_lds)
+            follow_groups<kGroupPairsPerThread>(get, E, R, G, n, target);
+        else
+            follow_groups(get, E, R, G, n, target);
     }
     __syncthreads();
     // phase 2: every start state through the G group mappings
@@ -1032,10 +1038,12 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     __syncthreads();
     const uint32_t E = K * TB;
     uint16_t *bmap = a.block_maps + (size_t)blockIdx.x * a.map_stride;
+    // mapping rows in global memory: the groups take the freed hot-image region
+    uint32_t *gscr = a.group_lds ? (uint32_t *)smem : s_scr;
     if (a.n_dfa <= 256)
-        compose_block<uint8_t, PARTIAL>(a, smem, s_ids, E, s_scr, bmap);
+        compose_block<uint8_t, PARTIAL>(a, smem, s_ids, E, gscr, bmap);
     else
-        compose_block<uint16_t, PARTIAL>(a, smem, s_ids, E, s_scr, bmap);
+        compose_block<uint16_t, PARTIAL>(a, smem, s_ids, E, gscr, bmap);
     block_done(a, smem, s_scr, s_flag);
 }
 

@@ -474,7 +474,7 @@ def batching_leg(seed: int, n_docs: int, plain_docs: int):
     }
 
 
-def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0)):
+def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0), big_bytes: int = 8 << 20):
     """Continuous-batching server vs the plain FIFO path under the same
     Poisson arrivals, at several multiples of the plain path's saturation rate."""
     import numpy as np
@@ -499,7 +499,7 @@ def serving_leg(seed: int, n_req: int, loads=(0.5, 0.8, 2.0, 4.0)):
         qps = mult * R
         reqs = W.c5_requests(seed, n_req=n_req, qps=qps)
         arrivals = [(r.arrival_s, r.table, r.data) for r in reqs]
-        srv = Server(backend, pool_bytes=1 << 30, max_inflight=3, big_bytes=8 << 20)
+        srv = Server(backend, pool_bytes=1 << 30, max_inflight=3, big_bytes=big_bytes)
         # no collector pauses inside either timed loop
         gc.collect()
         gc.disable()

@@ -237,6 +237,7 @@ class GpuBackend:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.next_stream = 0
         self.options = BatchOptions(piece_bytes, units_per_lane)
+        self.piece_bytes, self.units_per_lane = piece_bytes, units_per_lane
         # pinned result slots, reused round robin (more slots than batches in flight)
         self.result_slots = [torch.empty((max_batch_requests, 2), dtype=torch.int32, pin_memory=True)
                              for _ in range(result_slots)]
@@ -309,6 +310,15 @@ class GpuBackend:
     def batchable(self, table: int) -> bool:
         return table in self._batch_ids
 
+    def _options(self, total: int):
+        """Piece length for a batch of `total` bytes: a lane walks a piece one
+        byte after another, so a small batch is cut finer (about 16K pieces
+        per batch, 256 B to piece_bytes) and ends sooner."""
+        piece = 256
+        while piece < self.piece_bytes and piece * 2 * 16384 <= total:
+            piece *= 2
+        return self.BatchOptions(piece, self.units_per_lane)
+
     def launch_batch(self, requests, off):
         torch = self.torch
         if len(requests) == 1:
@@ -321,7 +331,7 @@ class GpuBackend:
         jobs = np.stack([np.arange(len(requests)), [self._batch_ids[r.table] for r in requests]],
                         axis=1).astype(np.uint32)
         with torch.cuda.stream(s):
-            b = self.Batch(self.batch_tables, doc_off, jobs, self.options, stream=s, ws=self.stream_ws[i],
+            b = self.Batch(self.batch_tables, doc_off, jobs, self._options(total), stream=s, ws=self.stream_ws[i],
                            out=self.stream_out[i])
             if b.ws is not self.stream_ws[i]:
                 self.stream_ws[i] = b.ws   # grown once for a larger plan, kept for the next ones

@@ -316,7 +316,7 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * (1,128,4) (2,64,2) (2,64,4) (2,128,2) (2,128,3) (2,128,4) (3,128,3)
  * (4,64,2) (8,32,2); TB=512: (1,64,2) (1,128,2) (1,128,3) (1,128,4) (2,64,2)
  * (2,64,4) (2,128,2) (2,128,3) (4,32,2) (4,64,2); TB=1024: (1,32,2) (1,64,2) (1,128,2) (2,32,2) (2,64,2).  The
- * default is (2,128,4,256); for a stride-4 table whose chunks are at most
+ * default is (2,128,3,512); for a stride-4 table whose chunks are at most
  * 4 KiB it is (1,128,2,512) with lanes_per_chunk raised until the lanes fill
  * one 512-thread block per CU, when ceil(n / n_chunks) is a multiple of
  * 128 * lanes_per_chunk.  Tables in global memory use lanes_per_chunk=1
@@ -326,8 +326,9 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * (1,64,2) (2,64,2) (1,128,2); default (4,128,1,512).  depth = 1 is a
  * rolling ring of three half-line slots per piece: every 128-byte line is
  * requested whole, with 1.5 lines of registers per piece.  With
- * n_chunks = 0 the default chunk count is one block of lanes per CU (four
- * for the global-table walk), with chunks of at least 1 KiB.
+ * n_chunks = 0 the default chunk count is one block of lanes per CU (five
+ * for the global-table walk when its chunks still hold at least 4 KiB,
+ * else four), with chunks of at least 1 KiB.
  * Other values give SFA_ERR_INVALID_ARG.  Short chunks lower K first. */
 typedef struct sfa_plan {
     uint32_t stride;

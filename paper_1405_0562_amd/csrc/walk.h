@@ -19,6 +19,7 @@ namespace sfa_rt {
 
 constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
 constexpr uint32_t kGlobalBlock = 512;       // default threads per block of the global-table walk
+constexpr uint32_t kLdsBlock = 512;          // default threads per block of the LDS walk
 constexpr uint64_t kShortChunk = 4096;       // chunk bytes up to which the stride-4 walk uses 512 threads
 constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
 constexpr uint32_t kDefaultLdsBudget = 96 * 1024;

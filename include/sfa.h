@@ -323,12 +323,20 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * with TB=256: (1,64,2) (2,64,2) (4,32,2) (4,64,2) (1,128,2) (2,128,2)
  * (4,128,2); TB=512: (1,64,2) (2,64,2) (4,32,2) (4,64,2) (1,128,2) (2,128,2)
  * (2,128,3) and the rolling rings (2,128,1) (3,128,1) (4,128,1); TB=1024:
- * (1,64,2) (2,64,2) (1,128,2); default (4,128,1,512).  depth = 1 is a
- * rolling ring of three half-line slots per piece: every 128-byte line is
- * requested whole, with 1.5 lines of registers per piece.  With
- * n_chunks = 0 the default chunk count is one block of lanes per CU (five
- * for the global-table walk when its chunks still hold at least 4 KiB,
- * else four), with chunks of at least 1 KiB.
+ * (1,64,2) (2,64,2) (1,128,2) and the rolling ring (2,128,1); default
+ * (2,128,1,1024) when n is at least 1 KiB x 1024 lanes x the CU count,
+ * else (4,128,1,512).  A partial D-SFA, and a table with vector re-walks
+ * (sfa_table_info.vector_redo), have kernels for (4,128,1,512),
+ * (2,128,1,512) and (1,64,2,512) only (vector re-walks: other shapes walk
+ * without them); their default is (4,128,1,512).  A plan that names a
+ * shape but not block_threads gets a block size that supports the shape.
+ * depth = 1 is a rolling ring of three half-line slots per piece: every
+ * 128-byte line is requested whole, with 1.5 lines of registers per piece.
+ * With n_chunks = 0 the default chunk count is one block of lanes per CU
+ * (for the global-table walk: with 1024-thread blocks four, two or one per
+ * CU, the most that keep chunks of at least 2 KiB; with 512-thread blocks
+ * five when the chunks still hold at least 4 KiB, else four), with chunks
+ * of at least 1 KiB.
  * Other values give SFA_ERR_INVALID_ARG.  Short chunks lower K first. */
 typedef struct sfa_plan {
     uint32_t stride;

@@ -753,21 +753,39 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
     bool any_img = false;
     for (const Image &im : t->L.img) any_img |= im.present != 0;
     const bool global_walk = !speculative && !any_img;
+    // Global-table walk: the default shape is (2, 128, 1) in 1024-thread
+    // blocks ("wide") when the input fills one such block per CU with chunks
+    // of at least 1 KiB; else, and for partial D-SFAs and tables with vector
+    // re-walks (kernels for the special shapes only), (4, 128, 1) in
+    // 512-thread blocks.  Measured on keyword text (ms, wide against 512):
+    // 4 GiB 1.61 / 1.73, 1 GiB 0.534 / 0.616, 256 MiB 0.181 / 0.215; 64 MiB
+    // 0.194 / 0.147 (half as many blocks as CUs).
+    const bool special = t->L.partial || t->L.vector_redo;
+    const uint64_t cus = std::max(1u, t->num_cus);
+    const bool wide = global_walk && !special && n >= cus * kGlobalBlock * 1024;
     if (n_chunks == 0) {
         const uint64_t target = speculative ? 4096 : 1024;   // bytes per chunk at least
         // default: one block of lanes per CU
-        // (the global-table walk: four or five blocks per CU, run one after
-        // another, which balances the CUs' end times better; measured on
-        // the 4 GiB keyword workload, blocks per CU 1: 1.99 ms, 2: 1.98,
-        // 3: 1.88, 4: 1.79, 5: 1.73, 6: 1.76, 8: 1.89.  Five only when its
-        // chunks still hold at least 8 whole 512-byte steps of four pieces
-        // (the chunk length then rounds to whole steps); else four, which
-        // splits power-of-two inputs into whole steps: 1 GiB r500 with five,
-        // pieces ending in single bytes, ran at half the rate)
-        const uint64_t cus = std::max(1u, t->num_cus);
+        // (the global-table walk: several blocks per CU, run one after
+        // another, which balances the CUs' end times better.  Wide: four,
+        // two or one, the most that keep chunks of at least 2 KiB; measured
+        // on 4 GiB of keyword text, blocks per CU 2: 1.695 ms, 3: 1.708, 4:
+        // 1.61-1.69, 4.5: 1.78, 5: 1.75; on 1 GiB 1: 0.54, 2: 0.534, 4:
+        // 0.651.  512-thread blocks: blocks per CU 1: 1.99 ms, 2: 1.98, 3:
+        // 1.88, 4: 1.79, 5: 1.73, 6: 1.76, 8: 1.89 on 4 GiB; five only when
+        // its chunks still hold at least 8 whole 512-byte steps of four
+        // pieces (the chunk length then rounds to whole steps); else four,
+        // which splits power-of-two inputs into whole steps: 1 GiB r500 with
+        // five, pieces ending in single bytes, ran at half the rate)
         const uint64_t p = std::max<uint64_t>(1, (n + target - 1) / target);
-        uint64_t per_cu = speculative ? kSpecWaves * 8 : global_walk ? 5 * kGlobalBlock : kLdsBlock;
-        if (global_walk && (n + cus * per_cu - 1) / (cus * per_cu) < 8 * 512) per_cu = 4 * kGlobalBlock;
+        uint64_t per_cu = speculative ? kSpecWaves * 8 : global_walk ? 5 * kGlobalSpecialBlock : kLdsBlock;
+        if (wide) {
+            uint64_t b = 4;
+            while (b > 1 && n / (cus * kGlobalBlock * b) < 2048) b /= 2;
+            per_cu = b * kGlobalBlock;
+        } else if (global_walk && (n + cus * per_cu - 1) / (cus * per_cu) < 8 * 512) {
+            per_cu = 4 * kGlobalSpecialBlock;
+        }
         P.n_chunks = (uint32_t)std::min(p, cus * per_cu);
     } else {
         P.n_chunks = n_chunks;
@@ -823,15 +841,28 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
         if (LPC == 0 || (LPC & (LPC - 1)) || LPC > 16)
             return sfa_fail(SFA_ERR_INVALID_ARG, "plan lanes_per_chunk must be a power of two <= 16");
         if (S == 0) {
-            // global-table walk: default (4, 128, 1) with 512 threads: two
-            // waves per SIMD share the staged rows and hide each other's LDS
-            // latency, and the rolling ring requests every 128-byte line
-            // whole (64-byte steps read a line in two visits, between which
-            // it leaves the L2: 1.94x the input bytes fetched, against 1.03x)
-            if (!user || !user->pieces) K = 4;
+            // global-table walk: default (2, 128, 1) with 1024 threads when
+            // wide: four waves per SIMD, two pieces each, share the staged
+            // rows and hide each other's LDS latency (4 GiB keyword text:
+            // 1.61 ms against 1.73 ms with (4, 128, 1) in 512-thread blocks,
+            // two waves of four pieces); else (4, 128, 1) with 512 threads.
+            // The rolling ring requests every 128-byte line whole (64-byte
+            // steps read a line in two visits, between which it leaves the
+            // L2: 1.94x the input bytes fetched, against 1.03x).
+            if (!user || !user->pieces) K = wide ? 2 : 4;
             if (!user || !user->load_bytes) G = 128;
             if (!user || !user->depth) D = 1;
-            if (!user || !user->block_threads) TB = kGlobalBlock;
+            if (!user || !user->block_threads) {
+                TB = wide ? kGlobalBlock : kGlobalSpecialBlock;
+                // a plan that names a shape but not its block size: the block
+                // size that supports it
+                if (!global_shape_ok(K, G, D, TB, t->L.partial))
+                    for (uint32_t tb : {512u, 256u, 1024u})
+                        if (global_shape_ok(K, G, D, tb, t->L.partial)) {
+                            TB = tb;
+                            break;
+                        }
+            }
             if (LPC != 1)
                 return sfa_fail(SFA_ERR_INVALID_ARG, "the global-table walk uses one lane per chunk");
             if (!global_shape_ok(K, G, D, TB, t->L.partial))

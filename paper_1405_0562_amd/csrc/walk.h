@@ -18,7 +18,8 @@ namespace sfa_rt {
 
 
 constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
-constexpr uint32_t kGlobalBlock = 512;       // default threads per block of the global-table walk
+constexpr uint32_t kGlobalBlock = 1024;      // threads per block of the global-table walk's wide default
+constexpr uint32_t kGlobalSpecialBlock = 512; // its other default (short inputs, partial D-SFAs, vector re-walks)
 constexpr uint32_t kLdsBlock = 512;          // default threads per block of the LDS walk
 constexpr uint64_t kShortChunk = 4096;       // chunk bytes up to which the stride-4 walk uses 512 threads
 constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
@@ -940,8 +941,10 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
                 for (int k = 0; k < K; ++k) t[k] = st[k], id[k] = sid[k];
                 // the class columns of the next word are read while this word
                 // is walked, unless the registers are short (the rolling ring
-                // with four pieces)
-                constexpr bool ahead = !(D == 1 && K >= 4);
+                // with four pieces, or with two in 1024-thread blocks: there
+                // the prefetch costs spills, 1.68 against 1.65 ms on 4 GiB of
+                // keyword text)
+                constexpr bool ahead = !(D == 1 && (K >= 4 || TB >= 1024));
                 uint32_t cc[4][K];
                 classes(cc, cur, 0);
 #pragma unroll
@@ -1070,7 +1073,7 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
     X(1, 64, 2, 512) X(2, 64, 2, 512) X(4, 32, 2, 512) X(4, 64, 2, 512) \
     X(1, 128, 2, 512) X(2, 128, 2, 512) X(2, 128, 3, 512) \
     X(2, 128, 1, 512) X(3, 128, 1, 512) X(4, 128, 1, 512) \
-    X(1, 64, 2, 1024) X(2, 64, 2, 1024) X(1, 128, 2, 1024)
+    X(1, 64, 2, 1024) X(2, 64, 2, 1024) X(1, 128, 2, 1024) X(2, 128, 1, 1024)
 
 // Shapes of the global-table walk for a partial (on-the-fly) D-SFA or a
 // table whose walk often leaves the hot rows (vector re-walks): the default

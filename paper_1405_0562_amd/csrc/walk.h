@@ -279,9 +279,14 @@ __device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem,
             follow_groups(get, E, R, 1, n, out_map);
             return;
         }
-        // rows from global memory: more chains at once to cover the latency
-        if (a.group_lds)
+        // rows from global memory: more chains at once to cover the latency,
+        // as many as the thread has pairs (up to kGroupPairsPerThread; a slot
+        // past the last pair repeats it, loads included)
+        const uint32_t per = (G * n + blockDim.x - 1) / blockDim.x;
+        if (a.group_lds && per > 8)
             follow_groups<kGroupPairsPerThread>(get, E, R, G, n, target);
+        else if (a.group_lds && per > 4)
+            follow_groups<8>(get, E, R, G, n, target);
         else
             follow_groups(get, E, R, G, n, target);
     }

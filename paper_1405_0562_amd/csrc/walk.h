@@ -285,8 +285,12 @@ __device__ __forceinline__ void compose_block(const MatchArgs &a, uint8_t *smem,
         const uint32_t per = (G * n + blockDim.x - 1) / blockDim.x;
         if (a.group_lds && per > 8)
             follow_groups<kGroupPairsPerThread>(get, E, R, G, n, target);
-        else if (a.group_lds && per > 4)
+        else if (a.group_lds && per > 6)
             follow_groups<8>(get, E, R, G, n, target);
+        else if (a.group_lds && per > 5)
+            follow_groups<6>(get, E, R, G, n, target);
+        else if (a.group_lds && per > 4)
+            follow_groups<5>(get, E, R, G, n, target);
         else
             follow_groups(get, E, R, G, n, target);
     }

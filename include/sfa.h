@@ -327,8 +327,9 @@ sfa_status sfa_match(const sfa_table *t, const uint8_t *d_in, uint64_t n, uint32
  * (2,128,1,1024) when n is at least 1 KiB x 1024 lanes x the CU count,
  * else (4,128,1,512).  A partial D-SFA, and a table with vector re-walks
  * (sfa_table_info.vector_redo), have kernels for (4,128,1,512),
- * (2,128,1,512) and (1,64,2,512) only (vector re-walks: other shapes walk
- * without them); their default is (4,128,1,512).  A plan that names a
+ * (2,128,1,512), (1,64,2,512) and (2,128,1,1024) only (vector re-walks:
+ * other shapes walk without them); a complete D-SFA with vector re-walks
+ * defaults to (4,128,1,512) at every size.  A plan that names a
  * shape but not block_threads gets a block size that supports the shape.
  * depth = 1 is a rolling ring of three half-line slots per piece: every
  * 128-byte line is requested whole, with 1.5 lines of registers per piece.

@@ -755,14 +755,14 @@ sfa_status make_plan(const sfa_table *t, uint64_t n, uint32_t n_chunks, bool spe
     const bool global_walk = !speculative && !any_img;
     // Global-table walk: the default shape is (2, 128, 1) in 1024-thread
     // blocks ("wide") when the input fills one such block per CU with chunks
-    // of at least 1 KiB; else, and for partial D-SFAs and tables with vector
-    // re-walks (kernels for the special shapes only), (4, 128, 1) in
-    // 512-thread blocks.  Measured on keyword text (ms, wide against 512):
-    // 4 GiB 1.61 / 1.73, 1 GiB 0.534 / 0.616, 256 MiB 0.181 / 0.215; 64 MiB
-    // 0.194 / 0.147 (half as many blocks as CUs).
-    const bool special = t->L.partial || t->L.vector_redo;
+    // of at least 1 KiB; else, and for complete D-SFAs with vector re-walks,
+    // (4, 128, 1) in 512-thread blocks.  Measured on keyword text (ms, wide
+    // against 512): 4 GiB 1.61 / 1.73, 1 GiB 0.534 / 0.616, 256 MiB 0.181 /
+    // 0.215; 64 MiB 0.194 / 0.147 (half as many blocks as CUs).  On-the-fly
+    // D-SFA of 60 keywords, 1 GiB: 8.9 / 13.1 ms; r500's complete D-SFA with
+    // vector re-walks, 1 GiB: 1.42 / 1.35 ms.
     const uint64_t cus = std::max(1u, t->num_cus);
-    const bool wide = global_walk && !special && n >= cus * kGlobalBlock * 1024;
+    const bool wide = global_walk && !(t->L.vector_redo && !t->L.partial) && n >= cus * kGlobalBlock * 1024;
     if (n_chunks == 0) {
         const uint64_t target = speculative ? 4096 : 1024;   // bytes per chunk at least
         // default: one block of lanes per CU

@@ -19,7 +19,7 @@ namespace sfa_rt {
 
 constexpr uint32_t kBlock = 256;             // threads per block of the walk kernels
 constexpr uint32_t kGlobalBlock = 1024;      // threads per block of the global-table walk's wide default
-constexpr uint32_t kGlobalSpecialBlock = 512; // its other default (short inputs, partial D-SFAs, vector re-walks)
+constexpr uint32_t kGlobalSpecialBlock = 512; // its other default (short inputs, complete D-SFAs with vector re-walks)
 constexpr uint32_t kLdsBlock = 512;          // default threads per block of the LDS walk
 constexpr uint64_t kShortChunk = 4096;       // chunk bytes up to which the stride-4 walk uses 512 threads
 constexpr uint32_t kSpecWaves = 4;           // waves (chunks) per speculative block
@@ -1086,8 +1086,8 @@ __global__ __launch_bounds__(TB) void k_sfa_global(MatchArgs a) {
 
 // Shapes of the global-table walk for a partial (on-the-fly) D-SFA or a
 // table whose walk often leaves the hot rows (vector re-walks): the default
-// plan and the shapes it falls back to for short chunks.
-#define SFA_SPECIAL_SHAPES(X) X(4, 128, 1, 512) X(2, 128, 1, 512) X(1, 64, 2, 512)
+// plans and the shapes they fall back to for short chunks.
+#define SFA_SPECIAL_SHAPES(X) X(4, 128, 1, 512) X(2, 128, 1, 512) X(1, 64, 2, 512) X(2, 128, 1, 1024)
 
 // Once per kernel and device (runtime.hip): checks that the kernel has no
 // static LDS (its dynamic LDS starts at address 0, which lds_u8/lds_u16

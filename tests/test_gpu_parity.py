@@ -365,7 +365,7 @@ GLOBAL_SHAPES = [(1, 64, 2, 256), (2, 64, 2, 256), (4, 32, 2, 256), (4, 64, 2, 2
                  (1, 64, 2, 512), (2, 64, 2, 512), (4, 32, 2, 512), (4, 64, 2, 512),
                  (1, 128, 2, 512), (2, 128, 2, 512), (2, 128, 3, 512),
                  (2, 128, 1, 512), (3, 128, 1, 512), (4, 128, 1, 512),
-                 (1, 64, 2, 1024), (2, 64, 2, 1024), (1, 128, 2, 1024)]
+                 (1, 64, 2, 1024), (2, 64, 2, 1024), (1, 128, 2, 1024), (2, 128, 1, 1024)]
 
 
 @pytest.mark.parametrize("product", [True, False])
@@ -392,12 +392,17 @@ def test_vector_rewalks_of_cold_words():
     full = sfa.load(sfa.compile(rx, sfa_cap=100_000), profile_sample=sample, lds_budget=2048)
     lazy = sfa.load(sfa.compile(rx, sfa_cap=0).build_lazy(sample, start_every=64, walk_bytes=512, max_states=2000),
                     profile_sample=sample, lds_budget=256)
+    wide = dict(pieces=2, load_bytes=128, depth=1, block_threads=1024)
     for t in (full, lazy):
         assert t.info["vector_redo"] == 1 and t.info["table_in_lds"] == 0
         for data in (words, words[: (1 << 20) + 77]):
             want = oracle_result(rx, data)
             for n_chunks in (0, 1000, 65536):
                 assert run_table(t, rx, data, n_chunks) == want, (t.info["partial"], n_chunks)
+            # the shape large inputs get by default (chunks of 1 KiB or more)
+            x = to_device(data)
+            for n_chunks in (500, 1000):
+                assert sfa.match(t, x, n_chunks=n_chunks, plan=wide).tolist() == want, (t.info["partial"], n_chunks)
 
 
 def test_dsfa_over_65536_states_uses_32_bit_ids():
